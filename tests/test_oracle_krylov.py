@@ -1,0 +1,119 @@
+"""Pins of the oracle Krylov solvers (P10) against library solvers and closed cases."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import h2gen
+from oracle import krylov
+from oracle.kernel import dense_G
+
+
+def _vie_matrix(n=6, side=0.5, eps_r=(2.0, 6.0), seed=3, sigma=1.0):
+    g = h2gen.cube(n, side, eps_r, seed=seed)
+    G = dense_G(g.shape, g.h, g.k)
+    chi = g.chi
+    Zs = np.eye(g.n_vox) + sigma * g.k ** 2 * g.volume * G * chi[None, :]
+    return np.kron(Zs, np.eye(3)), g
+
+
+def _scipy_iters(A, b, restart, tol):
+    count = [0]
+    x, info = spla.gmres(A, b, rtol=tol, atol=0.0, restart=restart, maxiter=1000,
+                         callback=lambda r: count.__setitem__(0, count[0] + 1), callback_type="pr_norm")
+    return x, count[0], info
+
+
+@pytest.mark.parametrize("restart", [50, 5])
+def test_gmres_matches_dense_solve_and_scipy(restart):
+    Z, g = _vie_matrix()
+    b = h2gen.random_vector(Z.shape[0], 11)
+    x, rep = krylov.gmres(lambda v: Z @ v, b, tol=1e-6, restart=restart)
+    xs = np.linalg.solve(Z, b)
+    cond = np.linalg.cond(Z)
+    assert rep.converged and rep.rel_residual <= 1e-6
+    assert np.linalg.norm(x - xs) <= 2 * cond * 1e-6 * np.linalg.norm(xs)
+    _, its, info = _scipy_iters(Z, b, restart, 1e-6)
+    assert info == 0
+    assert abs(rep.iterations - its) <= 1
+
+
+def test_gmres_identity_one_step():
+    b = h2gen.random_vector(300, 2)
+    x, rep = krylov.gmres(lambda v: v, b, tol=1e-6)
+    assert rep.iterations == 1 and np.allclose(x, b, atol=1e-14)
+
+
+def test_gmres_zero_contrast_is_identity():
+    Z, g = _vie_matrix(eps_r=1.0)
+    b = h2gen.random_vector(Z.shape[0], 4)
+    x, rep = krylov.gmres(lambda v: Z @ v, b)
+    assert rep.iterations == 1 and np.allclose(x, b, atol=1e-13)
+
+
+def test_gmres_lucky_breakdown_three_eigenvalues():
+    rng = np.random.default_rng(0)
+    Q, _ = np.linalg.qr(rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60)))
+    lam = np.repeat([1.0, 2.0 + 1j, 0.5j + 3.0], 20)
+    A = Q @ np.diag(lam) @ Q.conj().T
+    b = h2gen.random_vector(60, 5)
+    x, rep = krylov.gmres(lambda v: A @ v, b, tol=1e-12)
+    assert rep.iterations == 3 and rep.rel_residual < 1e-12
+
+
+def test_fgmres_exact_preconditioner_one_step():
+    Z, g = _vie_matrix()
+    Zi = np.linalg.inv(Z)
+    b = h2gen.random_vector(Z.shape[0], 6)
+    x, rep = krylov.gmres(lambda v: Z @ v, b, tol=1e-10, precond=lambda v: Zi @ v)
+    assert rep.iterations == 1 and rep.rel_residual < 1e-10
+
+
+def test_fgmres_linear_preconditioner_equals_gmres_on_right_preconditioned_system():
+    """With a fixed linear M, flexible GMRES on A equals GMRES on A M (x = M y)."""
+    Z, g = _vie_matrix(n=8, side=1.0)
+    N = Z.shape[0]
+    blk = 3 * 64
+    M = np.zeros_like(Z)
+    for i in range(0, N, blk):
+        M[i:i + blk, i:i + blk] = np.linalg.inv(Z[i:i + blk, i:i + blk])
+    b = h2gen.random_vector(N, 8)
+    x, r1 = krylov.gmres(lambda v: Z @ v, b, precond=lambda v: M @ v)
+    y, r2 = krylov.gmres(lambda v: Z @ (M @ v), b)
+    assert r1.converged and r2.converged
+    assert abs(r1.iterations - r2.iterations) <= 1
+    assert np.linalg.norm(x - M @ y) <= 1e-5 * np.linalg.norm(x)
+    assert np.linalg.norm(b - Z @ x) / np.linalg.norm(b) <= 1e-6
+
+
+def test_gmres_max_matvec_not_converged():
+    Z, g = _vie_matrix(sigma=-1.0, side=1.0)
+    b = h2gen.random_vector(Z.shape[0], 7)
+    x, rep = krylov.gmres(lambda v: Z @ v, b, tol=1e-12, restart=5, max_matvec=12)
+    assert not rep.converged and rep.matvecs <= 12
+    assert rep.rel_residual == pytest.approx(np.linalg.norm(b - Z @ x) / np.linalg.norm(b), rel=1e-10)
+
+
+def test_bicgstab_matches_solve():
+    Z, g = _vie_matrix()
+    b = h2gen.random_vector(Z.shape[0], 12)
+    x, rep = krylov.bicgstab(lambda v: Z @ v, b, tol=1e-8)
+    assert rep.converged
+    assert np.linalg.norm(x - np.linalg.solve(Z, b)) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_gmres_ir_reaches_high_precision_tolerance():
+    Z, g = _vie_matrix()
+    Zlo = (Z.astype(np.complex64)).astype(np.complex128)
+    b = h2gen.random_vector(Z.shape[0], 13)
+    x, info = krylov.gmres_ir(lambda v: Z @ v, lambda v: Zlo @ v, b, tol=1e-10, inner_tol=1e-3)
+    assert info["converged"] and info["outer"] >= 2
+    assert np.linalg.norm(b - Z @ x) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_givens_rotation():
+    for a, b in [(1 + 2j, 3 - 1j), (0j, 2j), (1j, 0j), (-0.3 + 0.1j, 1e-9)]:
+        c, s, r = krylov.givens(a, b)
+        R = np.array([[c, s], [-np.conj(s), c]])
+        out = R @ np.array([a, b])
+        assert abs(out[1]) < 1e-15 and abs(out[0] - r) < 1e-15
+        assert np.allclose(R @ R.conj().T, np.eye(2), atol=1e-15)
