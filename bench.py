@@ -1,0 +1,191 @@
+"""Benchmark: FP64 H^2 matvec/s (and HBM GB/s) on the 64^3 dielectric cube, N = 786432.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube64|cube32|cube12]
+
+One step is one full FP64 H^2 product y = Z x (prologue, leaf forward, upward
+pass, couplings at every level, downward pass, near field + leaf backward +
+epilogue) on the 4-wavelength cube (64^3 voxels x 3 components, eps_r ~ U[2,6]
+per voxel from seed 2, leaf 64, eta 1, eps 1e-3).  Inputs are synthetic and
+seeded; the representation is built on the host first (not timed) and
+resident in HBM when the timed region starts.  After the timed region the
+script times one GMRES(50) solve to 1e-6 per storage tier (plain FP64, and
+FP32 iterative refinement) on a seeded plane wave, checks the product against
+the CPU oracle, and times that oracle on the host (CPU baseline).  Rank 0
+prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (edge, side in wavelengths, eps_r spec, seed, eps)
+    "cube64": (64, 4.0, (2.0, 6.0), 2, 1e-3),
+    "cube32": (32, 2.0, (2.0, 6.0), 2, 1e-3),
+    "cube12": (12, 0.5, 4.0, 1, 1e-4),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def near_kernel_bytes(d) -> float:
+    """Algorithmic bytes of one near-field launch (FP64, 3 columns).
+
+    Per near block #t x #s: 16 #t #s bytes; plus, once per product, the leaf
+    bases (V_t read for the leaf backward), U (source values) read, x read and y
+    written for the epilogue (16 bytes per complex each).
+    """
+    n3 = 3 * int(d.n_vox)
+    return 16.0 * (d.near.size + d.basis.size) + 16.0 * 3 * n3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solves")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding plan is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import h2gen
+    from h2gen.construct import build_h2
+
+    edge, side, eps_r, seed, eps = WORKLOADS[args.workload]
+    # host construction first, before anything touches the GPU
+    g = h2gen.cube(edge, side, eps_r, seed=seed, name=args.workload)
+    t0 = time.time()
+    d = build_h2(g, eps=eps, verbose=True)
+    build_s = time.time() - t0
+    log(f"[bench] host construction {build_s:.1f}s")
+    x_np = h2gen.random_vector(3 * g.n_vox, 1)
+    b_np = h2gen.plane_wave(g, seed)[0]
+
+    import torch
+    from paper_1703_01175_amd import H2Operator
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0")
+    upload_s = time.time() - t0
+    st = H.stats()
+    log(f"[bench] upload {upload_s:.1f}s, device buffer {st['dev_bytes']/1e9:.2f} GB")
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        H.matvec(x, out=y)
+    torch.cuda.synchronize()
+    assert H.lib.h2_profile_enable(H.handle, 1) == 0
+    import ctypes as C
+    buf = (C.c_byte * 128)()
+    H.lib.h2_profile_read(H.handle, buf)       # reset
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        H.matvec(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    assert H.lib.h2_profile_read(H.handle, buf) == 0
+    fam_ms = np.frombuffer(bytes(buf)[:64], np.float64).copy()
+    fam_n = np.frombuffer(bytes(buf)[64:], np.int64).copy()
+    H.lib.h2_profile_enable(H.handle, 0)
+    ms_per = total_ms / args.steps
+    names = ["prologue", "leaf_forward", "upward", "coupling", "downward", "near_epilogue"]
+    fam = {names[i]: round(float(fam_ms[i] / max(fam_n[i], 1)), 4) for i in range(6)}
+    log(f"[bench] {ms_per:.3f} ms per product; per family (ms): {fam}")
+
+    near_ms = fam_ms[5] / max(fam_n[5], 1)
+    nb = near_kernel_bytes(d)
+    achieved = nb / (near_ms * 1e-3) / 1e9
+    coup_ms = fam_ms[3] / max(fam_n[3], 1)
+    coup_bytes = 16.0 * d.coupling.size + 4.0 * sum(int(r) for r in d.rank[d.far_s])
+    whole_gbs = st["bytes_fp64"] / (ms_per * 1e-3) / 1e9
+
+    result_gpu = y.cpu().numpy()
+    extra = {}
+    if not args.no_solve:
+        for prec in ("fp64", "fp32"):
+            bt = torch.from_numpy(b_np).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            xs, rep = H.gmres(bt, tol=1e-6, restart=50, precision=prec, inner_tol=1e-3)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            extra[f"gmres_{prec}"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
+                                          iterations=rep.iterations, matvecs=rep.matvecs, outer=rep.outer,
+                                          converged=rep.converged, rel_residual=rep.rel_residual)
+            log(f"[bench] GMRES {prec}: {dt:.3f}s, {rep.iterations} its, {rep.matvecs} products, "
+                f"residual {rep.rel_residual:.2e}")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        from oracle import matvec as om
+        t0 = time.time()
+        yo = om.h2_matvec(d, x_np)
+        cpu_s = time.time() - t0
+        parity = float(np.linalg.norm(result_gpu - yo) / np.linalg.norm(yo))
+        log(f"[bench] oracle product {cpu_s:.1f}s on the host, GPU vs oracle rel err {parity:.2e}")
+        cpu = {"value": round(1.0 / cpu_s, 6), "unit": "matvec/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full oracle FP64 product on the same {args.workload} representation "
+                         f"(N={3 * g.n_vox}), single Python thread",
+               "seconds": round(cpu_s, 3), "host_cpus": len(os.sched_getaffinity(0))}
+
+    out = {
+        "metric": "H^2 matvec/s (FP64, 3 field components) + HBM GB/s",
+        "value": round(1000.0 / ms_per, 4),
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {edge}^3 voxels, {side} wavelengths per side, "
+                               f"eps_r {eps_r}, seed {seed}, leaf 64, eta 1, eps {eps}",
+                   "N": 3 * g.n_vox, "n_rhs": 1, "precision": "fp64"},
+        "hbm_gbs_whole_product": round(whole_gbs, 2),
+        "algorithmic_bytes_per_product": st["bytes_fp64"],
+        "roofline": {"bound": "hbm", "kernel": "k_near_epilogue", "achieved": round(achieved, 2),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None, "bytes_per_launch": nb, "avg_ms": round(float(near_ms), 4)},
+        "coupling_kernel": {"avg_ms": round(float(coup_ms), 4),
+                            "achieved_gbs": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2) if coup_ms > 0 else None},
+        "kernel_ms": fam,
+        "cpu_baseline": cpu,
+        "parity_rel_err_vs_oracle": parity,
+        "host_build_s": round(build_s, 2),
+        "upload_s": round(upload_s, 2),
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * h2vie.h - C ABI of the MI355X H^2 volume-integral-equation hot path.
+ *
+ * The library applies, on one GPU, the minimal-rank H^2 representation of
+ * the VIE system matrix (Omar & Jiao, Sec. III-IV) and solves the system
+ * Z x = b with it (the paper's S D = E, eq. (2)):
+ *
+ *   Z x = x + sigma * k^2 * V * (G (x) I_ncomp) (chi . x),
+ *
+ * where G is the scalar Green's-function matrix between voxels held in H^2
+ * form: dense near-field (inadmissible) leaf blocks, nested orthonormal
+ * cluster bases (leaf bases V_t and transfer matrices T_c, eq. (9)) and one
+ * coupling matrix S_ts per admissible block (eq. (8)).  The product follows
+ * Sec. IV.B: forward transformation, coupling multiplication, backward
+ * transformation, plus full products of the inadmissible blocks.
+ *
+ * Conventions for every entry point:
+ *  - complex numbers are interleaved (re, im) doubles (FP64) unless a
+ *    precision argument says otherwise; matrices are column major;
+ *  - vectors live in device memory owned by the caller; unknown index
+ *    ncomp*i + c for voxel i (caller's voxel order) and component c; a block
+ *    of n_rhs vectors is column major with leading dimension ld >= N
+ *    (N = ncomp * n_vox), in complex elements;
+ *  - the stream argument is a hipStream_t passed as void* (NULL = null stream);
+ *    every call is stream ordered and returns once its work is enqueued,
+ *    except where a call says it synchronises;
+ *  - no exception crosses the ABI: each call returns an h2_status, and
+ *    h2_last_error() gives a thread-local message for the last failure;
+ *  - inputs are never modified; a handle is used by one stream at a time.
+ */
+#ifndef H2VIE_H
+#define H2VIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_handle_s* h2_handle;
+
+typedef enum {
+    H2_OK = 0,
+    H2_NOT_CONVERGED = 1,        /* warning: result written, tolerance not met */
+    H2_ERR_INVALID_ARG = -1,     /* null/misaligned pointer, bad size, unknown enum */
+    H2_ERR_BAD_DESC = -2,        /* host description inconsistent (indices, offsets, ranks) */
+    H2_ERR_DEVICE = -3,          /* a HIP runtime call failed */
+    H2_ERR_OOM = -4,             /* caller buffer smaller than the planned size */
+    H2_ERR_BAD_HANDLE = -5,      /* null or destroyed handle */
+    H2_ERR_NUMERIC = -6          /* NaN/Inf met in a solve */
+} h2_status;
+
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2 } h2_precision;
+typedef enum { H2_OP_G = 0, H2_OP_Z = 1 } h2_op;
+
+/*
+ * Host description of one H^2 representation (host memory, caller owned;
+ * read during h2_plan_from_host / h2_build_from_host only).
+ *
+ * Clusters c = 0..n_clusters-1 are numbered breadth first (root = 0); each
+ * owns the contiguous range [begin[c], end[c]) of tree positions, and
+ * perm[p] is the caller's voxel index at tree position p (Sec. III.A).
+ * rank[c] = k_c is the column count of the cluster basis (0 = unused).
+ *  - leaf bases V_c (#c x k_c, col major) at basis + 2*basis_off[c]
+ *    (basis_off = -1 for non-leaves or k_c = 0);
+ *  - transfer T_c (k_c x k_parent, col major) at transfer + 2*transfer_off[c]
+ *    (-1 where k_c or k_parent is 0);
+ *  - far (admissible) pairs i: (far_t[i], far_s[i]) with S (k_t x k_s, col
+ *    major) at coupling + 2*far_off[i].  All pairs of one row cluster t must be
+ *    consecutive and their S blocks stored back to back, i.e. the grouped
+ *    block row [S_ts1 S_ts2 ...] of t (eq. (5)) is one k_t x sum(k_s)
+ *    column-major matrix;
+ *  - near (inadmissible) pairs i: (near_t[i], near_s[i]), both leaves, with the
+ *    dense block G_ts (#t x #s, col major) at near + 2*near_off[i]; pairs are
+ *    sorted by near_t;
+ *  - chi[2*n_vox]: complex contrast eps_r - 1 per voxel (caller order);
+ *  - k (wavenumber), volume (voxel volume V), sigma (sign of the scattering
+ *    term, +1 or -1).
+ * Limits: ncomp == 3; leaf sizes <= 64; ranks <= 256; n_vox < 2^31.
+ */
+typedef struct {
+    int64_t n_vox;
+    int32_t ncomp;
+    int32_t n_clusters;
+    const int64_t* perm;
+    const int32_t* level;
+    const int32_t* parent;
+    const int64_t* begin;
+    const int64_t* end;
+    const int32_t* first_child;
+    const int32_t* nchild;
+    const int32_t* rank;
+    const int64_t* basis_off;
+    const double* basis;
+    int64_t basis_len;          /* complex elements */
+    const int64_t* transfer_off;
+    const double* transfer;
+    int64_t transfer_len;
+    int64_t n_far;
+    const int32_t* far_t;
+    const int32_t* far_s;
+    const int64_t* far_off;
+    const double* coupling;
+    int64_t coupling_len;
+    int64_t n_near;
+    const int32_t* near_t;
+    const int32_t* near_s;
+    const int64_t* near_off;
+    const double* near_blocks;
+    int64_t near_len;
+    const double* chi;
+    double k;
+    double volume;
+    double sigma;
+} h2_host_desc;
+
+typedef struct {
+    int32_t max_rhs;        /* most right-hand sides one call carries (>= 1) */
+    int32_t tiers;          /* bit mask (1 << h2_precision) of storage tiers to hold;
+                               FP64 is always held */
+} h2_build_opts;
+
+/* Size (bytes) of the device buffer h2_build_from_host needs for d and o.
+ * Validates d (same checks as the build).  Errors: INVALID_ARG, BAD_DESC. */
+h2_status h2_plan_from_host(const h2_host_desc* d, const h2_build_opts* o, size_t* dev_bytes);
+
+/* Validate d, pack it level by level into dev_buffer (caller-owned device
+ * memory of at least the planned size, 256-byte aligned) and return a handle
+ * that refers to that buffer.  Synchronises the stream before returning (the
+ * host staging memory is released).  Errors: INVALID_ARG, BAD_DESC, OOM
+ * (dev_bytes too small), DEVICE. */
+h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void* dev_buffer,
+                             size_t dev_bytes, void* stream, h2_handle* out);
+
+/* y = op(x) for n_rhs columns (Sec. IV.B product).  x, y: device,
+ * column major N x n_rhs, leading dimension ld (complex elements), in the
+ * precision's vector type (FP64: complex double; FP32 and BF16X3: complex
+ * float).  The block storage precision is p; accumulation is FP32 for FP32
+ * and BF16X3, FP64 otherwise.  x and y must not overlap.
+ * Errors: BAD_HANDLE, INVALID_ARG (n_rhs > max_rhs, ld < N, null, tier not
+ * built), DEVICE. */
+h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* y, int64_t n_rhs,
+                    int64_t ld, void* stream);
+
+typedef struct {
+    int32_t restart;        /* Krylov dimension m per cycle (1..128); 50 */
+    int32_t max_matvec;     /* budget of products with Z */
+    double tol;             /* relative residual ||b - Z x|| / ||b|| */
+    int32_t precision;      /* h2_precision of the inner products (FP64 = plain GMRES) */
+    double inner_tol;       /* inner tolerance of refinement when precision != FP64 */
+    int32_t max_outer;      /* refinement steps when precision != FP64 */
+} h2_gmres_opts;
+
+typedef struct {
+    int32_t converged;
+    int32_t iterations;     /* Arnoldi steps over all cycles and refinement steps */
+    int32_t matvecs;        /* products with Z (any precision) */
+    int32_t restarts;       /* GMRES cycles */
+    int32_t outer;          /* refinement steps (0 for FP64) */
+    double rel_residual;    /* true ||b - Z x|| / ||b||, FP64 product */
+} h2_gmres_report;
+
+/* Workspace bytes for h2_gmres_solve with opts o (device memory, caller owned). */
+h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes);
+
+/* Solve Z x = b for one right-hand side by restarted GMRES(m) with x0 = 0:
+ * Arnoldi by classical Gram-Schmidt applied twice, Givens rotations on the
+ * Hessenberg matrix, all on the device in FP64; the true residual b - Z x is
+ * formed after every cycle and decides convergence.  With precision FP32 or
+ * BF16X3 the solve is iterative refinement: r = b - Z x in FP64, an inner
+ * GMRES in FP64 arithmetic whose products use the lower-precision blocks,
+ * x += d.  b, x: device complex double, length N.  Synchronises the stream.
+ * Returns OK, NOT_CONVERGED (x holds the last iterate) or an error. */
+h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o,
+                         h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
+
+typedef struct {
+    int64_t n_vox, n_clusters, n_leaves, n_far, n_near, depth;
+    int64_t near_elems, coupling_elems, basis_elems, transfer_elems;  /* complex counts */
+    int64_t coef_rows;             /* sum of cluster ranks */
+    int32_t max_rank, min_leaf_rank;
+    int64_t dev_bytes;             /* planned buffer size */
+    double bytes_fp64;             /* algorithmic bytes of one FP64 product with 3 columns */
+    double flops_fp64;             /* real flops of one product with 3 columns */
+} h2_stats_t;
+
+h2_status h2_stats(h2_handle h, h2_stats_t* out);
+
+/* Kernel families of the product, in launch order. */
+enum {
+    H2_K_PROLOGUE = 0,      /* U = chi . x, tree permutation */
+    H2_K_LEAF_FORWARD = 1,  /* X_t = V_t^T U_t */
+    H2_K_UPWARD = 2,        /* X_p = sum T_c^T X_c */
+    H2_K_COUPLING = 3,      /* Y_t = sum S_ts X_s */
+    H2_K_DOWNWARD = 4,      /* Y_c += T_c Y_p */
+    H2_K_NEAR = 5,          /* near field + leaf backward + epilogue */
+    H2_K_FAMILIES = 8
+};
+
+typedef struct {
+    double ms[H2_K_FAMILIES];        /* summed device time per family */
+    int64_t launches[H2_K_FAMILIES]; /* launches per family */
+} h2_kernel_times;
+
+/* Diagnostics: with enable = 1, later products on h bracket every kernel
+ * family with HIP events on the product's stream; h2_profile_read waits for
+ * those events, returns the summed times since the last read, and resets
+ * them.  enable = 0 stops recording.  Errors: BAD_HANDLE, INVALID_ARG, DEVICE. */
+h2_status h2_profile_enable(h2_handle h, int enable);
+h2_status h2_profile_read(h2_handle h, h2_kernel_times* out);
+
+/* Release the handle's host metadata.  Never frees caller memory.  NULL is ignored. */
+void h2_destroy(h2_handle h);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2VIE_H */

@@ -1,0 +1,97 @@
+// Internal layout shared by the host packer (h2vie_api.cpp) and the HIP
+// kernels (h2_matvec.hip, h2_krylov.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h2 {
+
+constexpr int kNcomp = 3;        // field components per voxel
+constexpr int kMaxLeaf = 64;     // voxels per leaf cluster
+constexpr int kMaxRank = 256;    // cluster rank limit
+
+// Storage tier of the block data (near blocks, couplings, bases, transfers).
+struct TierData {
+    const void* near = nullptr;      // per near block, #t x #s column major
+    const void* coupling = nullptr;  // grouped block rows, k_t x sum(k_s) column major
+    const void* basis = nullptr;     // leaf bases, #t x k_t column major
+    const void* transfer = nullptr;  // T_c, k_c x k_parent column major
+    // BF16 hi+lo tier: low parts (same layout as the hi arrays above)
+    const void* near_lo = nullptr;
+    const void* coupling_lo = nullptr;
+    const void* basis_lo = nullptr;
+    const void* transfer_lo = nullptr;
+};
+
+// Everything a product needs, as device pointers into the caller's buffer.
+struct DevH2 {
+    int n_vox = 0;
+    int n_clusters = 0;
+    int n_leaves = 0;
+    int coef_rows = 0;          // sum of ranks
+    int n_rowcl = 0;            // row clusters of the coupling launch (rank > 0)
+    int depth = 0;
+    double k = 0, volume = 0, sigma = 1;
+
+    const int* perm = nullptr;          // [n_vox] tree position -> voxel
+    const double2* chi = nullptr;       // [n_vox] caller order
+
+    // clusters
+    const int* cl_rank = nullptr;
+    const int* cl_coef = nullptr;       // first coefficient row
+    const int* cl_begin = nullptr;
+    const int* cl_size = nullptr;
+    const int* cl_parent = nullptr;
+    const int* cl_first_child = nullptr;
+    const int* cl_nchild = nullptr;
+    const int64_t* cl_transfer_off = nullptr;  // complex offset of T_c (-1 none)
+    const int64_t* cl_basis_off = nullptr;     // complex offset of V_c (-1 none)
+
+    // leaves in launch order (most near blocks first)
+    const int* leaf_id = nullptr;       // [n_leaves]
+    const int* near_ptr = nullptr;      // [n_leaves + 1] into the near block list
+    const int* near_sbeg = nullptr;     // per near block: tree position of s
+    const int* near_ssize = nullptr;    // per near block: #s
+    const int64_t* near_off = nullptr;  // per near block: complex offset of G_ts
+
+    // coupling launch (row clusters, most work first)
+    const int* row_cl = nullptr;        // [n_rowcl]
+    const int* row_ncols = nullptr;     // grouped columns sum(k_s)
+    const int64_t* row_off = nullptr;   // complex offset of the grouped block row
+    const int* row_colptr = nullptr;    // first entry in colsrc
+    const int* colsrc = nullptr;        // coefficient row of each grouped column
+
+    // per-level lists for the upward / downward passes
+    const int* up_list = nullptr;       // parents with rank > 0, grouped by level (deepest first)
+    const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)
+
+    TierData tier[3];
+    bool has_tier[3] = {true, false, false};
+
+    // scratch for one product (3 * max_rhs columns)
+    void* U = nullptr;                  // [n_vox][ncols] tree order, vector type
+    void* Xh = nullptr;                 // [coef_rows][ncols]
+    void* Yh = nullptr;                 // [coef_rows][ncols]
+};
+
+// Host-side copies of the per-level launch sizes.
+struct LevelLaunch {
+    int up_begin[64], up_count[64];     // per level step (deepest first)
+    int down_begin[64], down_count[64]; // per level step (top first)
+    int n_up = 0, n_down = 0;
+};
+
+// Optional per-family event recording around kernel launches.
+struct Profiler {
+    virtual ~Profiler() {}
+    virtual void begin(int family, hipStream_t s) = 0;
+    virtual void end(int family, hipStream_t s) = 0;
+};
+
+// Launchers (h2_matvec.hip).  ncols = 3 * n_rhs columns are processed as
+// n_rhs passes of 3; x/y have leading dimension ld (complex elements).
+hipError_t launch_matvec(const DevH2& d, const LevelLaunch& lv, int op, int prec, const void* x,
+                         void* y, int64_t n_rhs, int64_t ld, hipStream_t s, Profiler* prof = nullptr);
+
+}  // namespace h2

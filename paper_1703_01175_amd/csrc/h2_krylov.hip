@@ -1,0 +1,487 @@
+// Restarted GMRES(m) around the H^2 product, on the device in FP64.
+//
+// The paper solves its VIE system iteratively with the O(N) H^2 product inside
+// the iteration (Sec. IV.B, Sec. V).  Each Arnoldi step here is
+//   w = Z v_j;  h = V^H w, w -= V h;  h' = V^H w, w -= V h', h += h'  (classical
+//   Gram-Schmidt applied twice);  v_{j+1} = w / ||w||;  Givens update of the
+//   Hessenberg column and of the residual estimate |g_{j+1}|.
+// A cycle ends at m steps, on breakdown, or when the estimate reaches the
+// tolerance; then y = R^-1 g, x += V y, and the true residual b - Z x decides.
+// With a lower-precision product the solve is iterative refinement: an FP64
+// outer residual and an inner GMRES (FP64 Arnoldi) on the FP32 / BF16 blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "h2_api_internal.h"
+
+namespace h2 {
+namespace {
+
+constexpr int kDotTile = 16;      // basis vectors per dot-product pass
+constexpr int kDotBlocks = 512;   // partial sums per vector
+
+__device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {   // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+template <int W>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_down(v, o, W);
+    return v;
+}
+
+// partial[blk][i] = sum over this block's elements of conj(V_i[n]) w[n], i in [i0, i0 + 16)
+__global__ __launch_bounds__(256) void k_multidot(const double2* __restrict__ V, int64_t ldv, int nvec,
+                                                  const double2* __restrict__ w, int64_t N,
+                                                  double2* __restrict__ partial) {
+    __shared__ double2 red[4][kDotTile];
+    const int i0 = blockIdx.y * kDotTile;
+    const int cnt = min(kDotTile, nvec - i0);
+    double2 acc[kDotTile];
+#pragma unroll
+    for (int q = 0; q < kDotTile; ++q) acc[q] = make_double2(0, 0);
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        const double2 wv = w[n];
+#pragma unroll
+        for (int q = 0; q < kDotTile; ++q)
+            if (q < cnt) {
+                double2 p = cmul_conj(V[(int64_t)(i0 + q) * ldv + n], wv);
+                acc[q].x += p.x;
+                acc[q].y += p.y;
+            }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kDotTile; ++q) {
+        double rx = wave_sum<64>(acc[q].x);
+        double ry = wave_sum<64>(acc[q].y);
+        if (lane == 0) red[wv][q] = make_double2(rx, ry);
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        const int q = threadIdx.x;
+        double2 s = red[0][q];
+        for (int k = 1; k < 4; ++k) { s.x += red[k][q].x; s.y += red[k][q].y; }
+        partial[(int64_t)blockIdx.x * 128 + i0 + q] = s;
+    }
+}
+
+// out[i] (+)= sum_blk partial[blk][i]
+__global__ void k_reduce_partial(const double2* __restrict__ partial, int nblk, int nvec, double2* __restrict__ out,
+                                 int accumulate) {
+    const int i = threadIdx.x;
+    if (i >= nvec) return;
+    double2 s = make_double2(0, 0);
+    for (int b = 0; b < nblk; ++b) { s.x += partial[(int64_t)b * 128 + i].x; s.y += partial[(int64_t)b * 128 + i].y; }
+    if (accumulate) { s.x += out[i].x; s.y += out[i].y; }
+    out[i] = s;
+}
+
+// w[n] += sign * sum_i V_i[n] c_i  (sign = -1: orthogonalise; +1: x += V y)
+// optional: partial squared norms of the result (nrm_partial[blockIdx.x])
+__global__ __launch_bounds__(256) void k_multiaxpy(const double2* __restrict__ V, int64_t ldv, int nvec,
+                                                   const double2* __restrict__ c, double sign, double2* __restrict__ w,
+                                                   int64_t N, double* __restrict__ nrm_partial) {
+    __shared__ double2 cs[128];
+    __shared__ double red[4];
+    for (int i = threadIdx.x; i < nvec; i += 256) cs[i] = c[i];
+    __syncthreads();
+    double nn = 0;
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        double2 a = make_double2(0, 0);
+        for (int i = 0; i < nvec; ++i) {
+            const double2 v = V[(int64_t)i * ldv + n];
+            const double2 ci = cs[i];
+            a.x = fma(v.x, ci.x, a.x);
+            a.x = fma(-v.y, ci.y, a.x);
+            a.y = fma(v.x, ci.y, a.y);
+            a.y = fma(v.y, ci.x, a.y);
+        }
+        double2 r = w[n];
+        r.x += sign * a.x;
+        r.y += sign * a.y;
+        w[n] = r;
+        nn += r.x * r.x + r.y * r.y;
+    }
+    if (nrm_partial) {
+        nn = wave_sum<64>(nn);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+        __syncthreads();
+        if (threadIdx.x == 0) nrm_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// r = b - z, partial squared norms
+__global__ __launch_bounds__(256) void k_residual(const double2* __restrict__ b, const double2* __restrict__ z,
+                                                  double2* __restrict__ r, int64_t N, double* __restrict__ nrm_partial) {
+    __shared__ double red[4];
+    double nn = 0;
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        double2 v = make_double2(b[n].x - z[n].x, b[n].y - z[n].y);
+        r[n] = v;
+        nn += v.x * v.x + v.y * v.y;
+    }
+    nn = wave_sum<64>(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) nrm_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// partial squared norms of a vector
+__global__ __launch_bounds__(256) void k_norm2(const double2* __restrict__ a, int64_t N, double* __restrict__ nrm_partial) {
+    __shared__ double red[4];
+    double nn = 0;
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        double2 v = a[n];
+        nn += v.x * v.x + v.y * v.y;
+    }
+    nn = wave_sum<64>(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) nrm_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// sum of partial norms -> scal[slot] = sqrt(sum)  (one wave, fixed order)
+__global__ void k_finish_norm(const double* __restrict__ partial, int nblk, double* __restrict__ scal, int slot) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[b];
+    s = wave_sum<64>(s);
+    if (threadIdx.x == 0) scal[slot] = sqrt(s);
+}
+
+// dst = src * (1 / scal[slot])
+__global__ void k_scale(const double2* __restrict__ src, double2* __restrict__ dst, int64_t N,
+                        const double* __restrict__ scal, int slot) {
+    const double inv = 1.0 / scal[slot];
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
+        dst[n] = make_double2(src[n].x * inv, src[n].y * inv);
+}
+
+__global__ void k_fill(double2* __restrict__ a, int64_t N) {
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
+        a[n] = make_double2(0, 0);
+}
+
+__global__ void k_add(double2* __restrict__ x, const double2* __restrict__ d, int64_t N) {
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x) {
+        x[n].x += d[n].x;
+        x[n].y += d[n].y;
+    }
+}
+
+// Givens update of Hessenberg column j (single thread; j < 128).
+// H is (m+1) x m column major; hcol holds h_0..h_j, scal[0] = ||w|| = h_{j+1}.
+// scal[1] = |g_{j+1}| (residual estimate, unnormalised).
+__global__ void k_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ hcol,
+                         double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                         double* __restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double2* col = H + (int64_t)j * ldh;
+    for (int i = 0; i <= j; ++i) col[i] = hcol[i];
+    col[j + 1] = make_double2(scal[0], 0.0);
+    for (int i = 0; i < j; ++i) {   // previous rotations
+        const double2 a = col[i], b = col[i + 1];
+        const double c = cs[i];
+        const double2 s = sn[i];
+        // [c s; -conj(s) c] [a; b]
+        col[i] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+        col[i + 1] = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+    }
+    const double2 a = col[j], b = col[j + 1];
+    const double aa = hypot(a.x, a.y), bb = hypot(b.x, b.y);
+    double c;
+    double2 s, r;
+    if (bb == 0.0) {
+        c = 1.0; s = make_double2(0, 0); r = a;
+    } else if (aa == 0.0) {
+        c = 0.0; s = make_double2(1.0, 0.0); r = b;
+    } else {
+        const double rho = hypot(aa, bb);
+        c = aa / rho;
+        const double2 ph = make_double2(a.x / aa, a.y / aa);          // a / |a|
+        s = make_double2((ph.x * b.x + ph.y * b.y) / rho, (ph.y * b.x - ph.x * b.y) / rho);  // ph * conj(b) / rho
+        r = make_double2(ph.x * rho, ph.y * rho);
+    }
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = r;
+    col[j + 1] = make_double2(0, 0);
+    const double2 gj = g[j];
+    // g_{j+1} = -conj(s) g_j ; g_j = c g_j
+    g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    g[j] = make_double2(c * gj.x, c * gj.y);
+    scal[1] = hypot(g[j + 1].x, g[j + 1].y);
+}
+
+// y = R^-1 g on the leading k x k triangle (single thread)
+__global__ void k_backsolve(const double2* __restrict__ H, int ldh, int k, const double2* __restrict__ g,
+                            double2* __restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double2 s = g[i];
+        for (int q = i + 1; q < k; ++q) {
+            const double2 h = H[(int64_t)q * ldh + i], yq = y[q];
+            s.x -= h.x * yq.x - h.y * yq.y;
+            s.y -= h.x * yq.y + h.y * yq.x;
+        }
+        const double2 d = H[(int64_t)i * ldh + i];
+        const double den = d.x * d.x + d.y * d.y;
+        y[i] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+    }
+}
+
+// g = (beta, 0, ..., 0)
+__global__ void k_init_g(double2* __restrict__ g, int m, const double* __restrict__ scal, int slot) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = make_double2(i == 0 ? scal[slot] : 0.0, 0.0);
+}
+
+struct Work {
+    double2 *V, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
+    float2 *lo_in, *lo_out;
+    double *cs, *scal, *npart;
+    double2* dpart;
+    int64_t ldv;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t work_layout(int64_t N, int m, Work* W, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const int64_t ldv = (N + 15) / 16 * 16;
+    Work w{};
+    w.ldv = ldv;
+    w.V = (double2*)take(size_t(ldv) * (m + 1) * 16);
+    w.w = (double2*)take(N * 16);
+    w.r = (double2*)take(N * 16);
+    w.z = (double2*)take(N * 16);
+    w.d = (double2*)take(N * 16);
+    w.xs = (double2*)take(N * 16);
+    w.lo_in = (float2*)take(N * 8);
+    w.lo_out = (float2*)take(N * 8);
+    w.hcol = (double2*)take(128 * 16);
+    w.H = (double2*)take(size_t(m + 1) * m * 16);
+    w.cs = (double*)take(128 * 8);
+    w.sn = (double2*)take(128 * 16);
+    w.g = (double2*)take(130 * 16);
+    w.y = (double2*)take(128 * 16);
+    w.scal = (double*)take(64 * 8);
+    w.npart = (double*)take(kDotBlocks * 8);
+    w.dpart = (double2*)take(size_t(kDotBlocks) * 128 * 16);
+    if (W) *W = w;
+    return off + 256;
+}
+
+struct Solver {
+    h2_handle h;
+    const DevH2* d;
+    const LevelLaunch* lv;
+    hipStream_t s;
+    int64_t N;
+    Work W;
+    double* host = nullptr;   // pinned host scalars
+    int nblk;
+
+    hipError_t matvec(int prec, const double2* x, double2* y) {
+        if (prec == 0) return launch_matvec(*d, *lv, 1, 0, x, y, 1, N, s);
+        hipError_t e = launch_vec_to_fp32(x, W.lo_in, N, s);
+        if (e != hipSuccess) return e;
+        e = launch_matvec(*d, *lv, 1, prec, W.lo_in, W.lo_out, 1, N, s);
+        if (e != hipSuccess) return e;
+        return launch_vec_to_fp64(W.lo_out, y, N, s);
+    }
+
+    hipError_t norm_into(const double2* a, int slot) {
+        k_norm2<<<nblk, 256, 0, s>>>(a, N, W.npart);
+        k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, slot);
+        return hipGetLastError();
+    }
+
+    hipError_t fetch(int count) {   // copy scal[0..count) to host and wait
+        hipError_t e = hipMemcpyAsync(host, W.scal, count * 8, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+
+    // V^H w for vectors 0..nvec-1 into out (accumulate or overwrite)
+    void multidot(int nvec, const double2* w, double2* out, int accumulate) {
+        dim3 grid(nblk, (nvec + kDotTile - 1) / kDotTile);
+        k_multidot<<<grid, 256, 0, s>>>(W.V, W.ldv, nvec, w, N, W.dpart);
+        k_reduce_partial<<<1, 128, 0, s>>>(W.dpart, nblk, nvec, out, accumulate);
+    }
+
+    // GMRES(m) on Z x = rhs with x0 = 0 (x overwritten).  prec: product tier.
+    // Returns status; fills its/mv/restarts and the final true relative residual.
+    h2_status gmres(int prec, const double2* rhs, double2* x, int m, int max_mv, double tol, int* its, int* mv,
+                    int* restarts, double* relres) {
+        hipError_t e;
+        *its = 0;
+        *mv = 0;
+        *restarts = 0;
+        k_fill<<<nblk, 256, 0, s>>>(x, N);
+        // r = rhs (x0 = 0)
+        e = hipMemcpyAsync(W.r, rhs, N * 16, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        (void)norm_into(rhs, 2);              // scal[2] = ||b||
+        (void)norm_into(W.r, 3);              // scal[3] = ||r||
+        if ((e = fetch(4)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        const double bnorm = host[2];
+        if (!std::isfinite(bnorm)) return handle_fail(H2_ERR_NUMERIC, "right-hand side holds NaN or Inf");
+        if (bnorm == 0.0) {
+            *relres = 0.0;
+            return H2_OK;
+        }
+        double beta = host[3];
+        while (true) {
+            *relres = beta / bnorm;
+            if (!std::isfinite(beta)) return handle_fail(H2_ERR_NUMERIC, "residual is NaN or Inf");
+            if (*relres <= tol) return H2_OK;
+            if (*mv >= max_mv) return H2_NOT_CONVERGED;
+            // v_0 = r / beta
+            k_scale<<<nblk, 256, 0, s>>>(W.r, W.V, N, W.scal, 3);
+            k_init_g<<<1, 256, 0, s>>>(W.g, m, W.scal, 3);
+            int jend = 0;
+            for (int j = 0; j < m; ++j) {
+                double2* vj = W.V + (int64_t)j * W.ldv;
+                if ((e = matvec(prec, vj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                ++*mv;
+                ++*its;
+                multidot(j + 1, W.w, W.hcol, 0);                                           // h = V^H w
+                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.hcol, -1.0, W.w, N, nullptr);
+                multidot(j + 1, W.w, W.y, 0);                                              // h' = V^H w
+                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.y, -1.0, W.w, N, W.npart);
+                k_reduce_partial<<<1, 128, 0, s>>>(W.y, 1, j + 1, W.hcol, 1);             // h += h'
+                k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);                 // ||w||
+                k_givens<<<1, 1, 0, s>>>(W.H, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal);
+                if ((e = fetch(2)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                jend = j + 1;
+                const double hn = host[0], est = host[1] / bnorm;
+                if (!std::isfinite(hn) || !std::isfinite(est)) return handle_fail(H2_ERR_NUMERIC, "Arnoldi produced NaN or Inf");
+                if (hn == 0.0 || est <= tol || *mv >= max_mv) break;
+                k_scale<<<nblk, 256, 0, s>>>(W.w, W.V + (int64_t)(j + 1) * W.ldv, N, W.scal, 0);
+            }
+            k_backsolve<<<1, 1, 0, s>>>(W.H, m + 1, jend, W.g, W.y);
+            k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y
+            // true residual r = rhs - Z x (product in the same tier)
+            if ((e = matvec(prec, x, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+            ++*mv;
+            k_residual<<<nblk, 256, 0, s>>>(rhs, W.z, W.r, N, W.npart);
+            k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 3);
+            if ((e = fetch(4)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+            beta = host[3];
+            ++*restarts;
+        }
+    }
+};
+
+}  // namespace
+}  // namespace h2
+
+using namespace h2;
+
+extern "C" h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes) {
+    if (!handle_live(h)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (!o || !bytes) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
+    if (o->restart < 1 || o->restart > 127) return handle_fail(H2_ERR_INVALID_ARG, "restart must be in [1, 127]");
+    const DevH2* d = handle_dev(h);
+    *bytes = work_layout(int64_t(d->n_vox) * kNcomp, o->restart, nullptr, nullptr);
+    return H2_OK;
+}
+
+extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o, h2_gmres_report* rep,
+                                    void* work, size_t work_bytes, void* stream) {
+    if (!handle_live(h)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (!b || !x || !o || !rep || !work) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
+    if (o->restart < 1 || o->restart > 127) return handle_fail(H2_ERR_INVALID_ARG, "restart must be in [1, 127]");
+    if (!(o->tol > 0.0) || o->max_matvec < 1) return handle_fail(H2_ERR_INVALID_ARG, "tol must be > 0 and max_matvec >= 1");
+    if (o->precision < H2_FP64 || o->precision > H2_BF16X3) return handle_fail(H2_ERR_INVALID_ARG, "unknown precision");
+    if ((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) % 16)
+        return handle_fail(H2_ERR_INVALID_ARG, "misaligned vector");
+    const DevH2* d = handle_dev(h);
+    if (!d->has_tier[o->precision]) return handle_fail(H2_ERR_INVALID_ARG, "precision tier was not built");
+    if (o->precision == H2_BF16X3) return handle_fail(H2_ERR_INVALID_ARG, "BF16X3 product is not available in this build");
+    const int64_t N = int64_t(d->n_vox) * kNcomp;
+    const int m = o->restart;
+    const size_t need = work_layout(N, m, nullptr, nullptr);
+    if (work_bytes < need) return handle_fail(H2_ERR_OOM, "GMRES workspace too small");
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~uintptr_t(255));
+    Solver S{};
+    S.h = h;
+    S.d = d;
+    S.lv = handle_levels(h);
+    S.s = reinterpret_cast<hipStream_t>(stream);
+    S.N = N;
+    S.nblk = int(std::min<int64_t>(kDotBlocks, (N + 255) / 256));
+    work_layout(N, m, &S.W, base);
+    if (hipHostMalloc((void**)&S.host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
+    *rep = h2_gmres_report{};
+    h2_status st;
+    const double2* bb = (const double2*)b;
+    double2* xx = (double2*)x;
+    if (o->precision == H2_FP64) {
+        int its, mv, rs;
+        double rr;
+        st = S.gmres(0, bb, xx, m, o->max_matvec, o->tol, &its, &mv, &rs, &rr);
+        rep->iterations = its;
+        rep->matvecs = mv;
+        rep->restarts = rs;
+        rep->rel_residual = rr;
+        rep->converged = (st == H2_OK);
+    } else {
+        // iterative refinement: r = b - Z x (FP64), inner GMRES with the low-precision product, x += d
+        st = H2_OK;
+        hipError_t e = hipSuccess;
+        k_fill<<<S.nblk, 256, 0, S.s>>>(xx, N);
+        (void)S.norm_into(bb, 2);
+        if ((e = S.fetch(3)) != hipSuccess) st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        const double bnorm = S.host[2];
+        if (st == H2_OK && !std::isfinite(bnorm)) st = handle_fail(H2_ERR_NUMERIC, "right-hand side holds NaN or Inf");
+        double rel = 0.0;
+        // rhs of the inner solve lives in W.xs (the residual), the correction in W.d
+        if (st == H2_OK && bnorm > 0) {
+            e = hipMemcpyAsync(S.W.xs, bb, N * 16, hipMemcpyDeviceToDevice, S.s);
+            rel = 1.0;
+            int outer = 0;
+            while (st == H2_OK) {
+                if (rel <= o->tol) break;
+                if (outer >= o->max_outer || rep->matvecs >= o->max_matvec) { st = H2_NOT_CONVERGED; break; }
+                int its, mv, rs;
+                double rr;
+                h2_status si = S.gmres(o->precision, S.W.xs, S.W.d, m, o->max_matvec - rep->matvecs, o->inner_tol,
+                                       &its, &mv, &rs, &rr);
+                if (si < 0) { st = si; break; }
+                rep->iterations += its;
+                rep->matvecs += mv;
+                rep->restarts += rs;
+                k_add<<<S.nblk, 256, 0, S.s>>>(xx, S.W.d, N);
+                if ((e = launch_matvec(*d, *S.lv, 1, 0, xx, S.W.z, 1, N, S.s)) != hipSuccess) {
+                    st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                    break;
+                }
+                rep->matvecs += 1;
+                k_residual<<<S.nblk, 256, 0, S.s>>>(bb, S.W.z, S.W.xs, N, S.W.npart);
+                k_finish_norm<<<1, 64, 0, S.s>>>(S.W.npart, S.nblk, S.W.scal, 3);
+                if ((e = S.fetch(4)) != hipSuccess) { st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e)); break; }
+                rel = S.host[3] / bnorm;
+                if (!std::isfinite(rel)) { st = handle_fail(H2_ERR_NUMERIC, "residual is NaN or Inf"); break; }
+                ++outer;
+            }
+            rep->outer = outer;
+        }
+        rep->rel_residual = rel;
+        rep->converged = (st == H2_OK);
+    }
+    if (hipStreamSynchronize(S.s) != hipSuccess && st >= 0) st = handle_fail(H2_ERR_DEVICE, "solve synchronisation failed");
+    (void)hipHostFree(S.host);
+    return st;
+}

@@ -1,0 +1,333 @@
+// H^2 matrix-vector product on gfx950 (Sec. IV.B of Omar & Jiao).
+//
+//   prologue      U = chi . x, permuted into tree order        (kappa(r') of eq. (1))
+//   leaf forward  X_t = V_t^T U_t                              (forward transformation)
+//   upward        X_p = sum_c T_c^T X_c, level by level         (nested bases, eq. (9))
+//   coupling      Y_t = sum_{s in R_t} S_ts X_s, all levels     (coupling multiplication)
+//   downward      Y_c += T_c Y_p, level by level                (backward transformation)
+//   near+leaf     y_t = sum_s G_ts U_s + V_t Y_t, then z = x + sigma k^2 V y (epilogue)
+//
+// Plain transposes (not conjugates) throughout, as the paper's transforms use
+// (V^s)^T.  Every kernel is templated on the block storage type TB and the
+// vector/accumulation type TV (double2 for FP64, float2 for FP32).
+#include <hip/hip_runtime.h>
+
+#include "h2_internal.h"
+
+namespace h2 {
+
+template <typename TV> struct Real;
+template <> struct Real<double2> { using T = double; };
+template <> struct Real<float2> { using T = float; };
+
+template <typename TV, typename TB>
+__device__ __forceinline__ void cfma(TV& acc, TB a, TV b) {
+    using R = typename Real<TV>::T;
+    R ax = (R)a.x, ay = (R)a.y;
+    acc.x = fma(ax, b.x, acc.x);
+    acc.x = fma(-ay, b.y, acc.x);
+    acc.y = fma(ax, b.y, acc.y);
+    acc.y = fma(ay, b.x, acc.y);
+}
+
+template <typename TV> __device__ __forceinline__ TV czero() { TV z; z.x = 0; z.y = 0; return z; }
+
+template <typename TV>
+__device__ __forceinline__ TV cadd(TV a, TV b) { TV r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+
+// ---------------------------------------------------------------- prologue
+// U[p][c] = chi[perm[p]] * x[3 perm[p] + c]  (op Z)   or   x[3 perm[p] + c]  (op G)
+template <typename TV>
+__global__ void k_prologue(int n_vox, const int* __restrict__ perm, const double2* __restrict__ chi,
+                           const TV* __restrict__ x, TV* __restrict__ U, int op) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_vox) return;
+    int v = perm[p];
+    using R = typename Real<TV>::T;
+    TV c;
+    if (op == 1) { c.x = (R)chi[v].x; c.y = (R)chi[v].y; } else { c.x = 1; c.y = 0; }
+#pragma unroll
+    for (int q = 0; q < kNcomp; ++q) {
+        TV a = x[(int64_t)v * kNcomp + q];
+        TV r;
+        r.x = c.x * a.x - c.y * a.y;
+        r.y = c.x * a.y + c.y * a.x;
+        U[(int64_t)p * kNcomp + q] = r;
+    }
+}
+
+// ---------------------------------------------------------------- leaf forward
+// X_t[a][c] = sum_i V_t[i, a] U_t[i][c]; one 64-thread group per leaf.
+template <typename TB, typename TV>
+__global__ __launch_bounds__(64) void k_leaf_forward(const int* __restrict__ leaf_id, const int* __restrict__ cl_rank,
+                                                     const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
+                                                     const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off,
+                                                     const TB* __restrict__ basis, const TV* __restrict__ U,
+                                                     TV* __restrict__ Xh) {
+    __shared__ TV su[kMaxLeaf * kNcomp];
+    const int t = leaf_id[blockIdx.x];
+    const int k = cl_rank[t];
+    if (k == 0) return;
+    const int n = cl_size[t];
+    const int b0 = cl_begin[t];
+    for (int e = threadIdx.x; e < n * kNcomp; e += 64) su[e] = U[(int64_t)b0 * kNcomp + e];
+    __syncthreads();
+    const TB* V = basis + cl_basis_off[t];
+    const int co = cl_coef[t];
+    for (int a = threadIdx.x; a < k; a += 64) {
+        TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+        const TB* col = V + (int64_t)a * n;
+        for (int i = 0; i < n; ++i) {
+            TB v = col[i];
+            cfma(acc0, v, su[i * 3 + 0]);
+            cfma(acc1, v, su[i * 3 + 1]);
+            cfma(acc2, v, su[i * 3 + 2]);
+        }
+        TV* o = Xh + (int64_t)(co + a) * kNcomp;
+        o[0] = acc0; o[1] = acc1; o[2] = acc2;
+    }
+}
+
+// ---------------------------------------------------------------- upward pass
+// X_p[a][c] = sum_children sum_b T_c[b, a] X_c[b][c]
+template <typename TB, typename TV>
+__global__ __launch_bounds__(64) void k_transfer_up(const int* __restrict__ list, const int* __restrict__ cl_rank,
+                                                    const int* __restrict__ cl_coef, const int* __restrict__ cl_first_child,
+                                                    const int* __restrict__ cl_nchild, const int64_t* __restrict__ cl_toff,
+                                                    const TB* __restrict__ transfer, TV* __restrict__ Xh) {
+    const int p = list[blockIdx.x];
+    const int kp = cl_rank[p];
+    const int c0 = cl_first_child[p], nc = cl_nchild[p];
+    for (int a = threadIdx.x; a < kp; a += 64) {
+        TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+        for (int ch = c0; ch < c0 + nc; ++ch) {
+            const int kc = cl_rank[ch];
+            if (kc == 0) continue;
+            const TB* T = transfer + cl_toff[ch] + (int64_t)a * kc;
+            const TV* xc = Xh + (int64_t)cl_coef[ch] * kNcomp;
+            for (int b = 0; b < kc; ++b) {
+                TB tv = T[b];
+                cfma(acc0, tv, xc[b * 3 + 0]);
+                cfma(acc1, tv, xc[b * 3 + 1]);
+                cfma(acc2, tv, xc[b * 3 + 2]);
+            }
+        }
+        TV* o = Xh + (int64_t)(cl_coef[p] + a) * kNcomp;
+        o[0] = acc0; o[1] = acc1; o[2] = acc2;
+    }
+}
+
+// ---------------------------------------------------------------- couplings
+// Y_t = [S_ts1 S_ts2 ...] * gather(X_s): the grouped block row of t (k_t x ncols,
+// column major) times the gathered coefficients.  256 threads: R rows x G column
+// groups (R = 16, 32 or 64 by rank), loads of one column are contiguous.
+template <typename TB, typename TV, int R>
+__device__ __forceinline__ void coupling_rows(int t, int kt, int ncols, const TB* __restrict__ S,
+                                              const int* __restrict__ src, const TV* __restrict__ Xh,
+                                              TV* __restrict__ Yh, int co, TV* red) {
+    constexpr int G = 256 / R;
+    const int a = threadIdx.x % R;
+    const int g = threadIdx.x / R;
+    for (int r0 = 0; r0 < kt; r0 += R) {
+        const int row = r0 + a;
+        TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+        if (row < kt) {
+            int col = g;
+#pragma unroll 4
+            for (; col < ncols; col += G) {
+                TB sv = S[(int64_t)col * kt + row];
+                const TV* xs = Xh + (int64_t)src[col] * kNcomp;
+                cfma(acc0, sv, xs[0]);
+                cfma(acc1, sv, xs[1]);
+                cfma(acc2, sv, xs[2]);
+            }
+        }
+        red[threadIdx.x * 3 + 0] = acc0; red[threadIdx.x * 3 + 1] = acc1; red[threadIdx.x * 3 + 2] = acc2;
+        __syncthreads();
+        if (threadIdx.x < R * 3) {
+            const int aa = threadIdx.x / 3, q = threadIdx.x % 3;
+            TV s = czero<TV>();
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) s = cadd(s, red[(gg * R + aa) * 3 + q]);
+            if (r0 + aa < kt) Yh[(int64_t)(co + r0 + aa) * kNcomp + q] = s;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_coupling(const int* __restrict__ row_cl, const int* __restrict__ row_ncols,
+                                                  const int64_t* __restrict__ row_off, const int* __restrict__ row_colptr,
+                                                  const int* __restrict__ colsrc, const int* __restrict__ cl_rank,
+                                                  const int* __restrict__ cl_coef, const TB* __restrict__ coupling,
+                                                  const TV* __restrict__ Xh, TV* __restrict__ Yh) {
+    __shared__ TV red[256 * 3];
+    const int slot = blockIdx.x;
+    const int t = row_cl[slot];
+    const int kt = cl_rank[t];
+    const int ncols = row_ncols[slot];
+    const TB* S = coupling + row_off[slot];
+    const int* src = colsrc + row_colptr[slot];
+    const int co = cl_coef[t];
+    if (kt <= 16)
+        coupling_rows<TB, TV, 16>(t, kt, ncols, S, src, Xh, Yh, co, red);
+    else if (kt <= 32)
+        coupling_rows<TB, TV, 32>(t, kt, ncols, S, src, Xh, Yh, co, red);
+    else
+        coupling_rows<TB, TV, 64>(t, kt, ncols, S, src, Xh, Yh, co, red);
+}
+
+// ---------------------------------------------------------------- downward pass
+// Y_c[b][c] += sum_a T_c[b, a] Y_p[a][c]
+template <typename TB, typename TV>
+__global__ __launch_bounds__(64) void k_transfer_down(const int* __restrict__ list, const int* __restrict__ cl_rank,
+                                                      const int* __restrict__ cl_coef, const int* __restrict__ cl_parent,
+                                                      const int64_t* __restrict__ cl_toff, const TB* __restrict__ transfer,
+                                                      TV* __restrict__ Yh) {
+    const int ch = list[blockIdx.x];
+    const int p = cl_parent[ch];
+    const int kc = cl_rank[ch], kp = cl_rank[p];
+    const TB* T = transfer + cl_toff[ch];
+    const TV* yp = Yh + (int64_t)cl_coef[p] * kNcomp;
+    for (int b = threadIdx.x; b < kc; b += 64) {
+        TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+        for (int a = 0; a < kp; ++a) {
+            TB tv = T[(int64_t)a * kc + b];
+            cfma(acc0, tv, yp[a * 3 + 0]);
+            cfma(acc1, tv, yp[a * 3 + 1]);
+            cfma(acc2, tv, yp[a * 3 + 2]);
+        }
+        TV* o = Yh + (int64_t)(cl_coef[ch] + b) * kNcomp;
+        o[0] = cadd(o[0], acc0); o[1] = cadd(o[1], acc1); o[2] = cadd(o[2], acc2);
+    }
+}
+
+// ---------------------------------------------------------------- near field + leaf backward + epilogue
+// One 256-thread group per leaf t; wave w streams near blocks w, w+4, ...;
+// lane i owns row i of every block (column-major blocks: coalesced columns).
+template <typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_near_epilogue(
+    const int* __restrict__ leaf_id, const int* __restrict__ near_ptr, const int* __restrict__ near_sbeg,
+    const int* __restrict__ near_ssize, const int64_t* __restrict__ near_off, const TB* __restrict__ near,
+    const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
+    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const TB* __restrict__ basis,
+    const TV* __restrict__ U, const TV* __restrict__ Yh, const int* __restrict__ perm, const TV* __restrict__ x,
+    TV* __restrict__ y, int op, typename Real<TV>::T alpha) {
+    __shared__ TV red[4][kMaxLeaf][3];
+    const int slot = blockIdx.x;
+    const int t = leaf_id[slot];
+    const int n = cl_size[t];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+    const int e = near_ptr[slot + 1];
+    for (int blk = near_ptr[slot] + w; blk < e; blk += 4) {
+        const int sb = near_sbeg[blk];
+        const int ns = near_ssize[blk];
+        const TB* Gb = near + near_off[blk];
+        const TV* us = U + (int64_t)sb * kNcomp;
+        if (lane < n) {
+#pragma unroll 8
+            for (int j = 0; j < ns; ++j) {
+                TB gv = Gb[(int64_t)j * n + lane];
+                cfma(acc0, gv, us[j * 3 + 0]);
+                cfma(acc1, gv, us[j * 3 + 1]);
+                cfma(acc2, gv, us[j * 3 + 2]);
+            }
+        }
+    }
+    red[w][lane][0] = acc0; red[w][lane][1] = acc1; red[w][lane][2] = acc2;
+    __syncthreads();
+    if (w == 0 && lane < n) {
+        TV s0 = cadd(cadd(red[0][lane][0], red[1][lane][0]), cadd(red[2][lane][0], red[3][lane][0]));
+        TV s1 = cadd(cadd(red[0][lane][1], red[1][lane][1]), cadd(red[2][lane][1], red[3][lane][1]));
+        TV s2 = cadd(cadd(red[0][lane][2], red[1][lane][2]), cadd(red[2][lane][2], red[3][lane][2]));
+        const int k = cl_rank[t];
+        if (k > 0) {   // backward transformation at the leaf: y_t += V_t Y_t
+            const TB* V = basis + cl_basis_off[t];
+            const TV* yt = Yh + (int64_t)cl_coef[t] * kNcomp;
+            for (int a = 0; a < k; ++a) {
+                TB v = V[(int64_t)a * n + lane];
+                cfma(s0, v, yt[a * 3 + 0]);
+                cfma(s1, v, yt[a * 3 + 1]);
+                cfma(s2, v, yt[a * 3 + 2]);
+            }
+        }
+        const int vox = perm[cl_begin[t] + lane];
+        TV* yo = y + (int64_t)vox * kNcomp;
+        if (op == 1) {
+            const TV* xi = x + (int64_t)vox * kNcomp;
+            TV r;
+            r.x = xi[0].x + alpha * s0.x; r.y = xi[0].y + alpha * s0.y; yo[0] = r;
+            r.x = xi[1].x + alpha * s1.x; r.y = xi[1].y + alpha * s1.y; yo[1] = r;
+            r.x = xi[2].x + alpha * s2.x; r.y = xi[2].y + alpha * s2.y; yo[2] = r;
+        } else {
+            yo[0] = s0; yo[1] = s1; yo[2] = s2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launcher
+template <typename TB, typename TV>
+static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, const TierData& td, const TV* x,
+                              TV* y, int64_t n_rhs, int64_t ld, hipStream_t s, Profiler* prof) {
+    using R = typename Real<TV>::T;
+    const TB* near = (const TB*)td.near;
+    const TB* coupling = (const TB*)td.coupling;
+    const TB* basis = (const TB*)td.basis;
+    const TB* transfer = (const TB*)td.transfer;
+    TV* U = (TV*)d.U;
+    TV* Xh = (TV*)d.Xh;
+    TV* Yh = (TV*)d.Yh;
+    const R alpha = (R)(d.sigma * d.k * d.k * d.volume);
+    auto begin = [&](int f) { if (prof) prof->begin(f, s); };
+    auto end = [&](int f) { if (prof) prof->end(f, s); };
+    for (int64_t r = 0; r < n_rhs; ++r) {
+        const TV* xr = x + r * ld;
+        TV* yr = y + r * ld;
+        begin(0);
+        k_prologue<TV><<<(d.n_vox + 255) / 256, 256, 0, s>>>(d.n_vox, d.perm, d.chi, xr, U, op);
+        end(0);
+        if (d.coef_rows > 0) {
+            begin(1);
+            k_leaf_forward<TB, TV><<<d.n_leaves, 64, 0, s>>>(d.leaf_id, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
+                                                             d.cl_basis_off, basis, U, Xh);
+            end(1);
+            begin(2);
+            for (int l = 0; l < lv.n_up; ++l)
+                if (lv.up_count[l] > 0)
+                    k_transfer_up<TB, TV><<<lv.up_count[l], 64, 0, s>>>(d.up_list + lv.up_begin[l], d.cl_rank, d.cl_coef,
+                                                                        d.cl_first_child, d.cl_nchild, d.cl_transfer_off,
+                                                                        transfer, Xh);
+            end(2);
+            begin(3);
+            k_coupling<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr, d.colsrc,
+                                                         d.cl_rank, d.cl_coef, coupling, Xh, Yh);
+            end(3);
+            begin(4);
+            for (int l = 0; l < lv.n_down; ++l)
+                if (lv.down_count[l] > 0)
+                    k_transfer_down<TB, TV><<<lv.down_count[l], 64, 0, s>>>(d.down_list + lv.down_begin[l], d.cl_rank,
+                                                                            d.cl_coef, d.cl_parent, d.cl_transfer_off,
+                                                                            transfer, Yh);
+            end(4);
+        }
+        begin(5);
+        k_near_epilogue<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off,
+                                                           near, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
+                                                           d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
+        end(5);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec(const DevH2& d, const LevelLaunch& lv, int op, int prec, const void* x, void* y,
+                         int64_t n_rhs, int64_t ld, hipStream_t s, Profiler* prof) {
+    if (prec == 0)
+        return matvec_tier<double2, double2>(d, lv, op, d.tier[0], (const double2*)x, (double2*)y, n_rhs, ld, s, prof);
+    if (prec == 1)
+        return matvec_tier<float2, float2>(d, lv, op, d.tier[1], (const float2*)x, (float2*)y, n_rhs, ld, s, prof);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace h2

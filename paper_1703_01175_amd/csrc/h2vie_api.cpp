@@ -1,0 +1,629 @@
+// Host side of the C ABI declared in include/h2vie.h: validation of the host
+// description, packing into the caller's device buffer, handles, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <mutex>
+#include <set>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/h2vie.h"
+#include "h2_internal.h"
+#include "h2_api_internal.h"
+
+using namespace h2;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+h2_status fail(h2_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+h2_status fail(h2_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+constexpr uint32_t kMagic = 0x48325649u;  // "H2VI"
+
+// Planned layout: every array at a 256-byte aligned offset of the device buffer.
+struct Layout {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = total;
+        total += (bytes + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+struct Plan {
+    // host staging (int arrays) and device offsets
+    std::vector<int> perm, cl_rank, cl_coef, cl_begin, cl_size, cl_parent, cl_first_child, cl_nchild;
+    std::vector<int64_t> cl_toff, cl_boff;
+    std::vector<int> leaf_id, near_ptr, near_sbeg, near_ssize;
+    std::vector<int64_t> near_off;
+    std::vector<int> row_cl, row_ncols, row_colptr, colsrc;
+    std::vector<int64_t> row_off;
+    std::vector<int> up_list, down_list;
+    LevelLaunch lv;
+    int coef_rows = 0, depth = 0, max_rank = 0, min_leaf_rank = 1 << 30;
+    int tiers = 1;
+    // device offsets
+    size_t o_perm, o_chi, o_cl[7], o_toff, o_boff, o_leaf, o_nptr, o_nsb, o_nss, o_noff;
+    size_t o_rowcl, o_rownc, o_rowcp, o_colsrc, o_rowoff, o_up, o_down;
+    size_t o_data[3][4];      // tier x {near, coupling, basis, transfer}
+    size_t o_data_lo[4];      // BF16 low parts
+    size_t o_U, o_X, o_Y, o_aux;
+    size_t aux_bytes = 0;
+    Layout lay;
+};
+
+inline bool bad_ptr(const void* p) { return p == nullptr; }
+
+h2_status validate(const h2_host_desc* d) {
+    if (!d) return fail(H2_ERR_INVALID_ARG, "null host description");
+    if (d->ncomp != kNcomp) return fail(H2_ERR_BAD_DESC, "ncomp must be 3 (got %d)", d->ncomp);
+    if (d->n_vox <= 0 || d->n_vox >= (int64_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "n_vox out of range");
+    if (d->n_clusters <= 0) return fail(H2_ERR_BAD_DESC, "n_clusters must be positive");
+    if (bad_ptr(d->perm) || bad_ptr(d->level) || bad_ptr(d->parent) || bad_ptr(d->begin) || bad_ptr(d->end) ||
+        bad_ptr(d->first_child) || bad_ptr(d->nchild) || bad_ptr(d->rank) || bad_ptr(d->basis_off) ||
+        bad_ptr(d->transfer_off) || bad_ptr(d->chi))
+        return fail(H2_ERR_INVALID_ARG, "null array in host description");
+    if ((d->n_far > 0 && (bad_ptr(d->far_t) || bad_ptr(d->far_s) || bad_ptr(d->far_off) || bad_ptr(d->coupling))) ||
+        (d->n_near > 0 && (bad_ptr(d->near_t) || bad_ptr(d->near_s) || bad_ptr(d->near_off) || bad_ptr(d->near_blocks))) ||
+        (d->basis_len > 0 && bad_ptr(d->basis)) || (d->transfer_len > 0 && bad_ptr(d->transfer)))
+        return fail(H2_ERR_INVALID_ARG, "null block array in host description");
+    if (d->n_far < 0 || d->n_near <= 0 || d->basis_len < 0 || d->transfer_len < 0 || d->coupling_len < 0 ||
+        d->near_len <= 0)
+        return fail(H2_ERR_BAD_DESC, "negative or empty sizes");
+    if (!std::isfinite(d->k) || !std::isfinite(d->volume) || !std::isfinite(d->sigma) || d->volume <= 0)
+        return fail(H2_ERR_BAD_DESC, "k, volume, sigma must be finite (volume > 0)");
+    const int64_t n = d->n_vox;
+    const int nc = d->n_clusters;
+    {
+        std::vector<char> seen(n, 0);
+        for (int64_t p = 0; p < n; ++p) {
+            int64_t v = d->perm[p];
+            if (v < 0 || v >= n || seen[v]) return fail(H2_ERR_BAD_DESC, "perm is not a permutation (position %lld)", (long long)p);
+            seen[v] = 1;
+        }
+    }
+    if (d->parent[0] != -1 || d->begin[0] != 0 || d->end[0] != n || d->level[0] != 0)
+        return fail(H2_ERR_BAD_DESC, "cluster 0 must be the root covering [0, n_vox)");
+    for (int c = 0; c < nc; ++c) {
+        if (d->begin[c] < 0 || d->end[c] > n || d->begin[c] >= d->end[c])
+            return fail(H2_ERR_BAD_DESC, "cluster %d has an invalid range", c);
+        if (d->rank[c] < 0 || d->rank[c] > kMaxRank) return fail(H2_ERR_BAD_DESC, "cluster %d rank out of [0, 256]", c);
+        if (c > 0) {
+            int p = d->parent[c];
+            if (p < 0 || p >= c) return fail(H2_ERR_BAD_DESC, "cluster %d parent must precede it", c);
+            if (d->level[c] != d->level[p] + 1) return fail(H2_ERR_BAD_DESC, "cluster %d level inconsistent", c);
+        }
+        if (d->level[c] < 0 || d->level[c] >= 63) return fail(H2_ERR_BAD_DESC, "cluster %d level out of range", c);
+        if (d->nchild[c] == 0) {
+            if (d->end[c] - d->begin[c] > kMaxLeaf) return fail(H2_ERR_BAD_DESC, "leaf %d larger than 64 voxels", c);
+            if (d->rank[c] > 0) {
+                int64_t o = d->basis_off[c];
+                int64_t need = (d->end[c] - d->begin[c]) * d->rank[c];
+                if (d->rank[c] > d->end[c] - d->begin[c]) return fail(H2_ERR_BAD_DESC, "leaf %d rank exceeds its size", c);
+                if (o < 0 || o + need > d->basis_len) return fail(H2_ERR_BAD_DESC, "leaf %d basis offset out of range", c);
+            }
+        } else {
+            int f = d->first_child[c], k = d->nchild[c];
+            if (k < 0 || f <= c || f + k > nc) return fail(H2_ERR_BAD_DESC, "cluster %d children out of range", c);
+            int64_t pos = d->begin[c];
+            for (int ch = f; ch < f + k; ++ch) {
+                if (d->parent[ch] != c || d->begin[ch] != pos)
+                    return fail(H2_ERR_BAD_DESC, "children of %d do not tile its range", c);
+                pos = d->end[ch];
+            }
+            if (pos != d->end[c]) return fail(H2_ERR_BAD_DESC, "children of %d do not tile its range", c);
+        }
+        if (c > 0) {
+            int p = d->parent[c];
+            if (d->rank[c] > 0 && d->rank[p] > 0) {
+                int64_t o = d->transfer_off[c];
+                int64_t need = int64_t(d->rank[c]) * d->rank[p];
+                if (o < 0 || o + need > d->transfer_len) return fail(H2_ERR_BAD_DESC, "transfer of %d out of range", c);
+            }
+        }
+    }
+    // far pairs: grouped by row cluster, contiguous grouped block rows
+    {
+        std::vector<char> done(nc, 0);
+        int64_t i = 0;
+        while (i < d->n_far) {
+            int t = d->far_t[i];
+            if (t < 0 || t >= nc) return fail(H2_ERR_BAD_DESC, "far pair %lld: row cluster out of range", (long long)i);
+            if (done[t]) return fail(H2_ERR_BAD_DESC, "far pairs of cluster %d are not consecutive", t);
+            done[t] = 1;
+            int kt = d->rank[t];
+            if (kt <= 0) return fail(H2_ERR_BAD_DESC, "far pair %lld: row cluster %d has rank 0", (long long)i, t);
+            int64_t off = d->far_off[i];
+            for (; i < d->n_far && d->far_t[i] == t; ++i) {
+                int s = d->far_s[i];
+                if (s < 0 || s >= nc) return fail(H2_ERR_BAD_DESC, "far pair %lld: column cluster out of range", (long long)i);
+                if (d->rank[s] <= 0) return fail(H2_ERR_BAD_DESC, "far pair %lld: column cluster %d has rank 0", (long long)i, s);
+                if (d->far_off[i] != off)
+                    return fail(H2_ERR_BAD_DESC, "far pair %lld: coupling blocks of row %d are not back to back", (long long)i, t);
+                off += int64_t(kt) * d->rank[s];
+                if (d->far_off[i] < 0 || off > d->coupling_len)
+                    return fail(H2_ERR_BAD_DESC, "far pair %lld: coupling offset out of range", (long long)i);
+            }
+        }
+    }
+    for (int64_t i = 0; i < d->n_near; ++i) {
+        int t = d->near_t[i], s = d->near_s[i];
+        if (t < 0 || t >= nc || s < 0 || s >= nc) return fail(H2_ERR_BAD_DESC, "near pair %lld out of range", (long long)i);
+        if (d->nchild[t] != 0 || d->nchild[s] != 0) return fail(H2_ERR_BAD_DESC, "near pair %lld is not leaf-leaf", (long long)i);
+        if (i > 0 && d->near_t[i - 1] > t) return fail(H2_ERR_BAD_DESC, "near pairs are not sorted by row cluster");
+        int64_t need = (d->end[t] - d->begin[t]) * (d->end[s] - d->begin[s]);
+        if (d->near_off[i] < 0 || d->near_off[i] + need > d->near_len)
+            return fail(H2_ERR_BAD_DESC, "near pair %lld: block offset out of range", (long long)i);
+    }
+    return H2_OK;
+}
+
+h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
+    h2_status st = validate(d);
+    if (st != H2_OK) return st;
+    if (!o) return fail(H2_ERR_INVALID_ARG, "null build options");
+    if (o->max_rhs < 1) return fail(H2_ERR_INVALID_ARG, "max_rhs must be >= 1");
+    if (o->tiers & ~7) return fail(H2_ERR_INVALID_ARG, "unknown tier bits 0x%x", o->tiers);
+    P.tiers = o->tiers | 1;
+    const int nc = d->n_clusters;
+    const int64_t n = d->n_vox;
+    P.perm.assign(n, 0);
+    for (int64_t p = 0; p < n; ++p) P.perm[p] = int(d->perm[p]);
+    P.cl_rank.assign(d->rank, d->rank + nc);
+    P.cl_coef.resize(nc);
+    P.cl_begin.resize(nc);
+    P.cl_size.resize(nc);
+    P.cl_parent.assign(d->parent, d->parent + nc);
+    P.cl_first_child.assign(d->first_child, d->first_child + nc);
+    P.cl_nchild.assign(d->nchild, d->nchild + nc);
+    P.cl_toff.assign(nc, -1);
+    P.cl_boff.assign(nc, -1);
+    int64_t coef = 0;
+    for (int c = 0; c < nc; ++c) {
+        P.cl_coef[c] = int(coef);
+        coef += d->rank[c];
+        P.cl_begin[c] = int(d->begin[c]);
+        P.cl_size[c] = int(d->end[c] - d->begin[c]);
+        P.depth = std::max(P.depth, int(d->level[c]));
+        P.max_rank = std::max(P.max_rank, d->rank[c]);
+        if (c > 0 && d->rank[c] > 0 && d->rank[d->parent[c]] > 0) P.cl_toff[c] = d->transfer_off[c];
+        if (d->nchild[c] == 0 && d->rank[c] > 0) P.cl_boff[c] = d->basis_off[c];
+    }
+    if (coef >= (int64_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "sum of ranks too large");
+    P.coef_rows = int(coef);
+
+    // leaves in launch order: most near blocks first
+    std::vector<int> leaves;
+    for (int c = 0; c < nc; ++c)
+        if (d->nchild[c] == 0) {
+            leaves.push_back(c);
+            P.min_leaf_rank = std::min(P.min_leaf_rank, d->rank[c]);
+        }
+    std::vector<int64_t> nfirst(nc, 0), ncount(nc, 0);
+    for (int64_t i = 0; i < d->n_near; ++i) {
+        int t = d->near_t[i];
+        if (ncount[t] == 0) nfirst[t] = i;
+        ncount[t]++;
+    }
+    std::stable_sort(leaves.begin(), leaves.end(), [&](int a, int b) { return ncount[a] > ncount[b]; });
+    P.leaf_id = leaves;
+    P.near_ptr.assign(1, 0);
+    for (int t : leaves) {
+        for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i) {
+            int s = d->near_s[i];
+            P.near_sbeg.push_back(int(d->begin[s]));
+            P.near_ssize.push_back(int(d->end[s] - d->begin[s]));
+            P.near_off.push_back(d->near_off[i]);
+        }
+        if (P.near_off.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many near blocks");
+        P.near_ptr.push_back(int(P.near_off.size()));
+    }
+
+    // coupling rows: every cluster with rank > 0 (rows without blocks produce zeros)
+    std::vector<int64_t> ffirst(nc, -1), fcount(nc, 0), fcols(nc, 0);
+    for (int64_t i = 0; i < d->n_far; ++i) {
+        int t = d->far_t[i];
+        if (ffirst[t] < 0) ffirst[t] = i;
+        fcount[t]++;
+        fcols[t] += d->rank[d->far_s[i]];
+    }
+    std::vector<int> rows;
+    for (int c = 0; c < nc; ++c)
+        if (d->rank[c] > 0) rows.push_back(c);
+    std::stable_sort(rows.begin(), rows.end(),
+                     [&](int a, int b) { return fcols[a] * d->rank[a] > fcols[b] * d->rank[b]; });
+    for (int t : rows) {
+        P.row_cl.push_back(t);
+        P.row_ncols.push_back(int(fcols[t]));
+        P.row_colptr.push_back(int(P.colsrc.size()));
+        P.row_off.push_back(ffirst[t] >= 0 ? d->far_off[ffirst[t]] : 0);
+        for (int64_t i = ffirst[t]; ffirst[t] >= 0 && i < ffirst[t] + fcount[t]; ++i) {
+            int s = d->far_s[i];
+            for (int b = 0; b < d->rank[s]; ++b) P.colsrc.push_back(P.cl_coef[s] + b);
+        }
+        if (P.colsrc.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many coupling columns");
+    }
+
+    // level lists: upward (deepest parents first), downward (top children first)
+    for (int l = P.depth - 1; l >= 0; --l) {
+        int b = int(P.up_list.size());
+        for (int c = 0; c < nc; ++c)
+            if (d->level[c] == l && d->nchild[c] > 0 && d->rank[c] > 0) P.up_list.push_back(c);
+        P.lv.up_begin[P.lv.n_up] = b;
+        P.lv.up_count[P.lv.n_up] = int(P.up_list.size()) - b;
+        P.lv.n_up++;
+    }
+    for (int l = 1; l <= P.depth; ++l) {
+        int b = int(P.down_list.size());
+        for (int c = 0; c < nc; ++c)
+            if (d->level[c] == l && P.cl_toff[c] >= 0) P.down_list.push_back(c);
+        P.lv.down_begin[P.lv.n_down] = b;
+        P.lv.down_count[P.lv.n_down] = int(P.down_list.size()) - b;
+        P.lv.n_down++;
+    }
+
+    // device layout
+    Layout& L = P.lay;
+    auto ints = [](size_t k) { return std::max<size_t>(k, 1) * sizeof(int); };
+    auto i64s = [](size_t k) { return std::max<size_t>(k, 1) * sizeof(int64_t); };
+    P.o_perm = L.add(ints(n));
+    P.o_chi = L.add(n * 16);
+    for (int q = 0; q < 7; ++q) P.o_cl[q] = L.add(ints(nc));
+    P.o_toff = L.add(i64s(nc));
+    P.o_boff = L.add(i64s(nc));
+    P.o_leaf = L.add(ints(P.leaf_id.size()));
+    P.o_nptr = L.add(ints(P.near_ptr.size()));
+    P.o_nsb = L.add(ints(P.near_sbeg.size()));
+    P.o_nss = L.add(ints(P.near_ssize.size()));
+    P.o_noff = L.add(i64s(P.near_off.size()));
+    P.o_rowcl = L.add(ints(P.row_cl.size()));
+    P.o_rownc = L.add(ints(P.row_ncols.size()));
+    P.o_rowcp = L.add(ints(P.row_colptr.size()));
+    P.o_colsrc = L.add(ints(P.colsrc.size()));
+    P.o_rowoff = L.add(i64s(P.row_off.size()));
+    P.o_up = L.add(ints(P.up_list.size()));
+    P.o_down = L.add(ints(P.down_list.size()));
+    const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
+    for (int tier = 0; tier < 3; ++tier)
+        for (int q = 0; q < 4; ++q) P.o_data[tier][q] = 0;
+    for (int q = 0; q < 4; ++q) P.o_data[0][q] = L.add(std::max<int64_t>(lens[q], 1) * 16);
+    if (P.tiers & 2)
+        for (int q = 0; q < 4; ++q) P.o_data[1][q] = L.add(std::max<int64_t>(lens[q], 1) * 8);
+    if (P.tiers & 4) {
+        for (int q = 0; q < 4; ++q) P.o_data[2][q] = L.add(std::max<int64_t>(lens[q], 1) * 4);
+        for (int q = 0; q < 4; ++q) P.o_data_lo[q] = L.add(std::max<int64_t>(lens[q], 1) * 4);
+    }
+    const size_t cols = size_t(kNcomp);
+    P.o_U = L.add(size_t(n) * cols * 16);
+    P.o_X = L.add(size_t(std::max(P.coef_rows, 1)) * cols * 16);
+    P.o_Y = L.add(size_t(std::max(P.coef_rows, 1)) * cols * 16);
+    P.aux_bytes = aux_scratch_bytes(n, P.coef_rows);
+    P.o_aux = L.add(P.aux_bytes);
+    return H2_OK;
+}
+
+// Event pairs around kernel families; read back (and summed) on demand.
+struct EventProfiler : Profiler {
+    struct Rec { int family; hipEvent_t a, b; };
+    std::vector<Rec> open, done;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int family, hipStream_t s) override {
+        hipEvent_t a = take();
+        if (!a) return;
+        (void)hipEventRecord(a, s);
+        open.push_back({family, a, nullptr});
+    }
+    void end(int family, hipStream_t s) override {
+        for (size_t i = open.size(); i-- > 0;)
+            if (open[i].family == family && open[i].b == nullptr) {
+                hipEvent_t b = take();
+                if (!b) return;
+                (void)hipEventRecord(b, s);
+                open[i].b = b;
+                done.push_back(open[i]);
+                open.erase(open.begin() + i);
+                return;
+            }
+    }
+    ~EventProfiler() override {
+        for (auto& r : done) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto& r : open) (void)hipEventDestroy(r.a);
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+struct h2_handle_s {
+    uint32_t magic = kMagic;
+    DevH2 dev;
+    LevelLaunch lv;
+    h2_stats_t stats{};
+    char* base = nullptr;
+    size_t bytes = 0;
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
+    int tiers = 1;
+    EventProfiler* prof = nullptr;
+    ~h2_handle_s() { delete prof; }
+};
+
+// Live handles: a destroyed or foreign pointer is rejected before it is read.
+static std::mutex g_handles_mu;
+static std::set<h2_handle> g_handles;
+
+static bool handle_ok(h2_handle h) {
+    if (h == nullptr) return false;
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return g_handles.count(h) != 0 && h->magic == kMagic;
+}
+
+extern "C" {
+
+const char* h2_last_error(void) { return g_last_error.c_str(); }
+
+h2_status h2_plan_from_host(const h2_host_desc* d, const h2_build_opts* o, size_t* dev_bytes) {
+    if (!dev_bytes) return fail(H2_ERR_INVALID_ARG, "null dev_bytes");
+    Plan P;
+    h2_status st = make_plan(d, o, P);
+    if (st != H2_OK) return st;
+    *dev_bytes = P.lay.total + 256;
+    return H2_OK;
+}
+
+h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void* dev_buffer, size_t dev_bytes,
+                             void* stream, h2_handle* out) {
+    if (!out) return fail(H2_ERR_INVALID_ARG, "null output handle pointer");
+    *out = nullptr;
+    if (!dev_buffer) return fail(H2_ERR_INVALID_ARG, "null device buffer");
+    Plan P;
+    h2_status st = make_plan(d, o, P);
+    if (st != H2_OK) return st;
+    uintptr_t b = (reinterpret_cast<uintptr_t>(dev_buffer) + 255) & ~uintptr_t(255);
+    size_t lost = b - reinterpret_cast<uintptr_t>(dev_buffer);
+    if (dev_bytes < P.lay.total + lost) return fail(H2_ERR_OOM, "device buffer of %zu bytes, %zu needed", dev_bytes, P.lay.total + lost);
+    char* base = reinterpret_cast<char*>(b);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    std::vector<hipError_t> errs;
+    const int nc = d->n_clusters;
+    errs.push_back(put(P.o_perm, P.perm.data(), P.perm.size() * 4));
+    errs.push_back(put(P.o_chi, d->chi, size_t(d->n_vox) * 16));
+    const std::vector<int>* cl[7] = {&P.cl_rank, &P.cl_coef, &P.cl_begin, &P.cl_size, &P.cl_parent, &P.cl_first_child, &P.cl_nchild};
+    for (int q = 0; q < 7; ++q) errs.push_back(put(P.o_cl[q], cl[q]->data(), size_t(nc) * 4));
+    errs.push_back(put(P.o_toff, P.cl_toff.data(), size_t(nc) * 8));
+    errs.push_back(put(P.o_boff, P.cl_boff.data(), size_t(nc) * 8));
+    errs.push_back(put(P.o_leaf, P.leaf_id.data(), P.leaf_id.size() * 4));
+    errs.push_back(put(P.o_nptr, P.near_ptr.data(), P.near_ptr.size() * 4));
+    errs.push_back(put(P.o_nsb, P.near_sbeg.data(), P.near_sbeg.size() * 4));
+    errs.push_back(put(P.o_nss, P.near_ssize.data(), P.near_ssize.size() * 4));
+    errs.push_back(put(P.o_noff, P.near_off.data(), P.near_off.size() * 8));
+    errs.push_back(put(P.o_rowcl, P.row_cl.data(), P.row_cl.size() * 4));
+    errs.push_back(put(P.o_rownc, P.row_ncols.data(), P.row_ncols.size() * 4));
+    errs.push_back(put(P.o_rowcp, P.row_colptr.data(), P.row_colptr.size() * 4));
+    errs.push_back(put(P.o_colsrc, P.colsrc.data(), P.colsrc.size() * 4));
+    errs.push_back(put(P.o_rowoff, P.row_off.data(), P.row_off.size() * 8));
+    errs.push_back(put(P.o_up, P.up_list.data(), P.up_list.size() * 4));
+    errs.push_back(put(P.o_down, P.down_list.data(), P.down_list.size() * 4));
+    const double* src[4] = {d->near_blocks, d->coupling, d->basis, d->transfer};
+    const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
+    for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_data[0][q], src[q], size_t(lens[q]) * 16));
+    for (hipError_t e : errs)
+        if (e != hipSuccess) return fail(H2_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    // lower-precision tiers converted on the device from the FP64 copy
+    for (int q = 0; q < 4; ++q) {
+        if (lens[q] == 0) continue;
+        if (P.tiers & 2) {
+            hipError_t e = launch_convert_fp32((const double2*)(base + P.o_data[0][q]), (float2*)(base + P.o_data[1][q]), lens[q], s);
+            if (e != hipSuccess) return fail(H2_ERR_DEVICE, "fp32 conversion failed: %s", hipGetErrorString(e));
+        }
+        if (P.tiers & 4) {
+            hipError_t e = launch_split_bf16((const double2*)(base + P.o_data[0][q]), (uint32_t*)(base + P.o_data[2][q]),
+                                             (uint32_t*)(base + P.o_data_lo[q]), lens[q], s);
+            if (e != hipSuccess) return fail(H2_ERR_DEVICE, "bf16 split failed: %s", hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(H2_ERR_DEVICE, "build synchronisation failed: %s", hipGetErrorString(e));
+
+    h2_handle h = new h2_handle_s();
+    DevH2& D = h->dev;
+    D.n_vox = int(d->n_vox);
+    D.n_clusters = nc;
+    D.n_leaves = int(P.leaf_id.size());
+    D.coef_rows = P.coef_rows;
+    D.n_rowcl = int(P.row_cl.size());
+    D.depth = P.depth;
+    D.k = d->k;
+    D.volume = d->volume;
+    D.sigma = d->sigma;
+    D.perm = (const int*)(base + P.o_perm);
+    D.chi = (const double2*)(base + P.o_chi);
+    D.cl_rank = (const int*)(base + P.o_cl[0]);
+    D.cl_coef = (const int*)(base + P.o_cl[1]);
+    D.cl_begin = (const int*)(base + P.o_cl[2]);
+    D.cl_size = (const int*)(base + P.o_cl[3]);
+    D.cl_parent = (const int*)(base + P.o_cl[4]);
+    D.cl_first_child = (const int*)(base + P.o_cl[5]);
+    D.cl_nchild = (const int*)(base + P.o_cl[6]);
+    D.cl_transfer_off = (const int64_t*)(base + P.o_toff);
+    D.cl_basis_off = (const int64_t*)(base + P.o_boff);
+    D.leaf_id = (const int*)(base + P.o_leaf);
+    D.near_ptr = (const int*)(base + P.o_nptr);
+    D.near_sbeg = (const int*)(base + P.o_nsb);
+    D.near_ssize = (const int*)(base + P.o_nss);
+    D.near_off = (const int64_t*)(base + P.o_noff);
+    D.row_cl = (const int*)(base + P.o_rowcl);
+    D.row_ncols = (const int*)(base + P.o_rownc);
+    D.row_colptr = (const int*)(base + P.o_rowcp);
+    D.colsrc = (const int*)(base + P.o_colsrc);
+    D.row_off = (const int64_t*)(base + P.o_rowoff);
+    D.up_list = (const int*)(base + P.o_up);
+    D.down_list = (const int*)(base + P.o_down);
+    for (int tier = 0; tier < 3; ++tier) {
+        D.has_tier[tier] = (P.tiers >> tier) & 1;
+        if (!D.has_tier[tier]) continue;
+        D.tier[tier].near = base + P.o_data[tier][0];
+        D.tier[tier].coupling = base + P.o_data[tier][1];
+        D.tier[tier].basis = base + P.o_data[tier][2];
+        D.tier[tier].transfer = base + P.o_data[tier][3];
+    }
+    if (P.tiers & 4) {
+        D.tier[2].near_lo = base + P.o_data_lo[0];
+        D.tier[2].coupling_lo = base + P.o_data_lo[1];
+        D.tier[2].basis_lo = base + P.o_data_lo[2];
+        D.tier[2].transfer_lo = base + P.o_data_lo[3];
+    }
+    D.U = base + P.o_U;
+    D.Xh = base + P.o_X;
+    D.Yh = base + P.o_Y;
+    h->aux = base + P.o_aux;
+    h->aux_bytes = P.aux_bytes;
+    h->lv = P.lv;
+    h->base = base;
+    h->bytes = P.lay.total;
+    h->tiers = P.tiers;
+    h2_stats_t& S = h->stats;
+    S.n_vox = d->n_vox;
+    S.n_clusters = nc;
+    S.n_leaves = D.n_leaves;
+    S.n_far = d->n_far;
+    S.n_near = d->n_near;
+    S.depth = P.depth;
+    S.near_elems = d->near_len;
+    S.coupling_elems = d->coupling_len;
+    S.basis_elems = d->basis_len;
+    S.transfer_elems = d->transfer_len;
+    S.coef_rows = P.coef_rows;
+    S.max_rank = P.max_rank;
+    S.min_leaf_rank = P.min_leaf_rank;
+    S.dev_bytes = int64_t(P.lay.total + 256);
+    const double blocks = double(d->near_len + d->coupling_len + d->basis_len + d->transfer_len);
+    S.bytes_fp64 = (blocks + 2.0 * double(d->n_vox) * kNcomp) * 16.0;
+    S.flops_fp64 = 8.0 * kNcomp * (double(d->near_len) + double(d->coupling_len) + 2.0 * double(d->basis_len) +
+                                   2.0 * double(d->transfer_len));
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        g_handles.insert(h);
+    }
+    *out = h;
+    return H2_OK;
+}
+
+h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* y, int64_t n_rhs, int64_t ld,
+                    void* stream) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (op != H2_OP_G && op != H2_OP_Z) return fail(H2_ERR_INVALID_ARG, "unknown op %d", int(op));
+    if (p < H2_FP64 || p > H2_BF16X3) return fail(H2_ERR_INVALID_ARG, "unknown precision %d", int(p));
+    if (!h->dev.has_tier[p]) return fail(H2_ERR_INVALID_ARG, "precision tier %d was not built", int(p));
+    if (!x || !y) return fail(H2_ERR_INVALID_ARG, "null vector");
+    const int64_t N = int64_t(h->dev.n_vox) * kNcomp;
+    if (n_rhs < 1) return fail(H2_ERR_INVALID_ARG, "n_rhs must be >= 1");
+    if (ld < N) return fail(H2_ERR_INVALID_ARG, "ld (%lld) < N (%lld)", (long long)ld, (long long)N);
+    const size_t esz = (p == H2_FP64) ? 16 : 8;
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % esz)
+        return fail(H2_ERR_INVALID_ARG, "misaligned vector");
+    const char* xb = (const char*)x;
+    const char* yb = (const char*)y;
+    const size_t span = size_t((n_rhs - 1) * ld + N) * esz;
+    if (xb < yb + span && yb < xb + span) return fail(H2_ERR_INVALID_ARG, "x and y overlap");
+    hipError_t e = launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld, reinterpret_cast<hipStream_t>(stream),
+                                 h->prof);
+    if (e != hipSuccess) return fail(H2_ERR_DEVICE, "matvec launch failed: %s", hipGetErrorString(e));
+    return H2_OK;
+}
+
+h2_status h2_profile_enable(h2_handle h, int enable) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (enable && !h->prof) h->prof = new EventProfiler();
+    if (!enable && h->prof) {
+        if (hipDeviceSynchronize() != hipSuccess) return fail(H2_ERR_DEVICE, "synchronisation failed");
+        delete h->prof;
+        h->prof = nullptr;
+    }
+    return H2_OK;
+}
+
+h2_status h2_profile_read(h2_handle h, h2_kernel_times* out) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (!out) return fail(H2_ERR_INVALID_ARG, "null output");
+    *out = h2_kernel_times{};
+    if (!h->prof) return H2_OK;
+    for (auto& r : h->prof->done) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(H2_ERR_DEVICE, "event synchronisation failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(H2_ERR_DEVICE, "event timing failed");
+        if (r.family >= 0 && r.family < H2_K_FAMILIES) {
+            out->ms[r.family] += ms;
+            out->launches[r.family] += 1;
+        }
+        h->prof->pool.push_back(r.a);
+        h->prof->pool.push_back(r.b);
+    }
+    h->prof->done.clear();
+    return H2_OK;
+}
+
+h2_status h2_stats(h2_handle h, h2_stats_t* out) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (!out) return fail(H2_ERR_INVALID_ARG, "null stats");
+    *out = h->stats;
+    return H2_OK;
+}
+
+void h2_destroy(h2_handle h) {
+    if (!handle_ok(h)) return;
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        g_handles.erase(h);
+    }
+    h->magic = 0;
+    delete h;
+}
+
+}  // extern "C"
+
+// accessors used by the solver translation unit
+namespace h2 {
+const DevH2* handle_dev(h2_handle h) { return handle_ok(h) ? &h->dev : nullptr; }
+const LevelLaunch* handle_levels(h2_handle h) { return handle_ok(h) ? &h->lv : nullptr; }
+void* handle_aux(h2_handle h, size_t* bytes) {
+    if (!handle_ok(h)) return nullptr;
+    *bytes = h->aux_bytes;
+    return h->aux;
+}
+bool handle_live(h2_handle h) { return handle_ok(h); }
+h2_status handle_fail(h2_status st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
+}  // namespace h2

@@ -1,0 +1,127 @@
+"""GPU parity of the H^2 product through the C ABI against the CPU oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import h2gen
+from conftest import built
+from oracle import matvec as om
+from oracle import precision as oprec
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["cube8", "cube12", "cube12_e3", "rod", "slab", "cube13", "box9", "cube16"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+_OPS = {}
+
+
+def operator(name, tiers=("fp64", "fp32")):
+    from paper_1703_01175_amd import H2Operator
+    key = (name, tiers)
+    if key not in _OPS:
+        g, d = built(name)
+        _OPS[key] = (g, d, H2Operator(d, tiers=tiers, max_rhs=4))
+    return _OPS[key]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("op", ["Z", "G"])
+def test_fp64_product_matches_oracle(torch, name, op):
+    print(f"[gpu] fp64 product {name} op {op}", flush=True)
+    g, d, H = operator(name)
+    x = h2gen.random_vector(3 * g.n_vox, 17)
+    y = H.matvec(torch.from_numpy(x).cuda(), op=op).cpu().numpy()
+    yo = om.h2_matvec(d, x, op)
+    assert _rel(y, yo) <= 1e-12
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_multiple_rhs(torch):
+    g, d, H = operator("slab")
+    X = h2gen.random_vector(3 * g.n_vox, 5, ncols=3)          # (3, N): column major N x 3
+    Y = H.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = om.h2_matvec(d, X.T.copy()).T
+    assert _rel(Y, Yo) <= 1e-12
+
+
+def test_plane_wave_product(torch):
+    g, d, H = operator("cube12")
+    b = h2gen.plane_wave(g, 3)[0]
+    y = H.matvec(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert _rel(y, om.h2_matvec(d, b)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["cube12", "rod", "cube16"])
+def test_fp32_tier_error(torch, name):
+    g, d, H = operator(name)
+    x = h2gen.random_vector(3 * g.n_vox, 23)
+    yo = om.h2_matvec(d, x)
+    y32 = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
+    emu = oprec.h2_matvec_tier(d, x, "fp32")
+    e_gpu, e_emu = _rel(y32, yo), _rel(emu, yo)
+    print(f"[gpu] fp32 tier {name}: gpu {e_gpu:.2e} emulated {e_emu:.2e}")
+    assert e_gpu <= 1e-5 and e_gpu <= 2.0 * e_emu + 1e-7
+
+
+def test_build_rejects_small_buffer(torch):
+    import ctypes as C
+    from paper_1703_01175_amd import _lib
+    g, d = built("rod")
+    lib = _lib.load()
+    hd, keep = _lib.host_desc(d)
+    opts = _lib.BuildOpts(1, 1)
+    n = C.c_size_t(0)
+    assert lib.h2_plan_from_host(C.byref(hd), C.byref(opts), C.byref(n)) == 0
+    buf = torch.empty(n.value // 2, dtype=torch.uint8, device="cuda")
+    h = C.c_void_p(0)
+    st = lib.h2_build_from_host(C.byref(hd), C.byref(opts), C.c_void_p(buf.data_ptr()), n.value // 2,
+                                None, C.byref(h))
+    assert st == -4 and not h.value
+
+
+def test_destroyed_handle_and_bad_args(torch):
+    from paper_1703_01175_amd import H2Operator
+    g, d = built("rod")
+    H = H2Operator(d)                                   # FP64 tier only
+    x = torch.from_numpy(h2gen.random_vector(3 * g.n_vox, 1)).cuda()
+    y = torch.empty_like(x)
+    lib = H.lib
+    assert lib.h2_matvec(H.handle, 1, 1, x.data_ptr(), y.data_ptr(), 1, H.N, None) == -1   # tier not built
+    assert lib.h2_matvec(H.handle, 1, 0, x.data_ptr(), x.data_ptr(), 1, H.N, None) == -1   # x, y overlap
+    assert lib.h2_matvec(H.handle, 1, 0, x.data_ptr(), y.data_ptr(), 1, H.N - 1, None) == -1  # ld < N
+    assert lib.h2_matvec(H.handle, 7, 0, x.data_ptr(), y.data_ptr(), 1, H.N, None) == -1   # unknown op
+    assert lib.h2_matvec(H.handle, 1, 0, x.data_ptr() + 8, y.data_ptr(), 1, H.N, None) == -1  # misaligned
+    handle = H.handle
+    H.close()
+    assert lib.h2_matvec(handle, 1, 0, x.data_ptr(), y.data_ptr(), 1, H.N, None) == -5
+
+
+def test_profile_counts_kernel_families(torch):
+    import ctypes as C
+    from paper_1703_01175_amd import _lib
+    g, d, H = operator("cube16")
+    lib = H.lib
+    assert lib.h2_profile_enable(H.handle, 1) == 0
+    x = torch.from_numpy(h2gen.random_vector(3 * g.n_vox, 2)).cuda()
+    for _ in range(3):
+        H.matvec(x)
+    buf = (C.c_byte * 128)()
+    assert lib.h2_profile_read(H.handle, buf) == 0
+    ms = np.frombuffer(bytes(buf)[:64], np.float64)
+    launches = np.frombuffer(bytes(buf)[64:], np.int64)
+    assert launches[5] == 3 and launches[0] == 3 and ms[5] > 0
+    assert lib.h2_profile_enable(H.handle, 0) == 0
