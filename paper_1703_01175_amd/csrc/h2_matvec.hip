@@ -32,6 +32,32 @@ __device__ __forceinline__ void cfma(TV& acc, TB a, TV b) {
 
 template <typename TV> __device__ __forceinline__ TV czero() { TV z; z.x = 0; z.y = 0; return z; }
 
+// Streaming (nontemporal) loads of block data: read once per product, kept out
+// of the caches that hold the reused vectors.
+__device__ __forceinline__ double2 ldnt(const double2* p) {
+    return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ float2 ldnt(const float2* p) {
+    return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+
+// Broadcast lane J of each 16-lane row to the whole row (DPP row_newbcast).
+template <int J> __device__ __forceinline__ double bcast_row(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x150 + J, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x150 + J, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int J> __device__ __forceinline__ float bcast_row(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, false));
+}
+template <int J, typename TV> __device__ __forceinline__ TV bcast_row2(TV v) {
+    TV r;
+    r.x = bcast_row<J>(v.x);
+    r.y = bcast_row<J>(v.y);
+    return r;
+}
+
 template <typename TV>
 __device__ __forceinline__ TV cadd(TV a, TV b) { TV r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
 
@@ -119,37 +145,79 @@ __global__ __launch_bounds__(64) void k_transfer_up(const int* __restrict__ list
 
 // ---------------------------------------------------------------- couplings
 // Y_t = [S_ts1 S_ts2 ...] * gather(X_s): the grouped block row of t (k_t x ncols,
-// column major) times the gathered coefficients.  256 threads: R rows x G column
-// groups (R = 16, 32 or 64 by rank), loads of one column are contiguous.
+// column major) times the gathered coefficients.  A wave is G = 64/R column
+// groups of R row lanes (R = 16, 32 or 64 by rank).  Per super-step of 16*G
+// columns, lane i of every 16-lane DPP row fetches the coefficients of one
+// column (column base + G*i + g of its group g), and step j broadcasts lane j's
+// coefficients across the row while every lane streams S(row, base + G*j + g):
+// each load instruction covers G consecutive columns of the column-major block.
+template <int J, typename TB, typename TV>
+__device__ __forceinline__ void coup_step(const TB* sv, TV x0, TV x1, TV x2, TV& a0, TV& a1, TV& a2) {
+    TV b0 = bcast_row2<J>(x0), b1 = bcast_row2<J>(x1), b2 = bcast_row2<J>(x2);
+    cfma(a0, sv[J], b0);
+    cfma(a1, sv[J], b1);
+    cfma(a2, sv[J], b2);
+}
+
 template <typename TB, typename TV, int R>
-__device__ __forceinline__ void coupling_rows(int t, int kt, int ncols, const TB* __restrict__ S,
-                                              const int* __restrict__ src, const TV* __restrict__ Xh,
-                                              TV* __restrict__ Yh, int co, TV* red) {
-    constexpr int G = 256 / R;
-    const int a = threadIdx.x % R;
-    const int g = threadIdx.x / R;
+__device__ __forceinline__ void coupling_rows(int kt, int ncols, const TB* __restrict__ S, const int* __restrict__ src,
+                                              const TV* __restrict__ Xh, TV* __restrict__ Yh, int co, TV* red) {
+    constexpr int G = 64 / R;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int a = lane % R;
+    const int g = lane / R;
+    const int i16 = lane & 15;
     for (int r0 = 0; r0 < kt; r0 += R) {
         const int row = r0 + a;
+        const bool live = row < kt;
         TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
-        if (row < kt) {
-            int col = g;
-#pragma unroll 4
-            for (; col < ncols; col += G) {
-                TB sv = S[(int64_t)col * kt + row];
-                const TV* xs = Xh + (int64_t)src[col] * kNcomp;
-                cfma(acc0, sv, xs[0]);
-                cfma(acc1, sv, xs[1]);
-                cfma(acc2, sv, xs[2]);
+        for (int base = w * 16 * G; base < ncols; base += 4 * 16 * G) {
+            const int cx = base + G * i16 + g;
+            TV x0 = czero<TV>(), x1 = czero<TV>(), x2 = czero<TV>();
+            if (cx < ncols) {
+                const TV* xs = Xh + (int64_t)src[cx] * kNcomp;
+                x0 = xs[0];
+                x1 = xs[1];
+                x2 = xs[2];
             }
+            TB sv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = base + G * q + g;
+                if (live && c < ncols) sv[q] = ldnt(S + (int64_t)c * kt + row);
+                else { sv[q].x = 0; sv[q].y = 0; }
+            }
+            coup_step<0>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<1>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<2>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<3>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<4>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<5>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<6>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<7>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<8>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<9>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<10>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<11>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<12>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<13>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<14>(sv, x0, x1, x2, acc0, acc1, acc2);
+            coup_step<15>(sv, x0, x1, x2, acc0, acc1, acc2);
         }
-        red[threadIdx.x * 3 + 0] = acc0; red[threadIdx.x * 3 + 1] = acc1; red[threadIdx.x * 3 + 2] = acc2;
+        // threadIdx.x = w*64 + g*R + a: reduce over the 4 waves and G groups of each row
+        red[threadIdx.x * 3 + 0] = acc0;
+        red[threadIdx.x * 3 + 1] = acc1;
+        red[threadIdx.x * 3 + 2] = acc2;
         __syncthreads();
         if (threadIdx.x < R * 3) {
             const int aa = threadIdx.x / 3, q = threadIdx.x % 3;
-            TV s = czero<TV>();
+            TV sum = czero<TV>();
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) s = cadd(s, red[(gg * R + aa) * 3 + q]);
-            if (r0 + aa < kt) Yh[(int64_t)(co + r0 + aa) * kNcomp + q] = s;
+            for (int ww = 0; ww < 4; ++ww)
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) sum = cadd(sum, red[(ww * 64 + gg * R + aa) * 3 + q]);
+            if (r0 + aa < kt) Yh[(int64_t)(co + r0 + aa) * kNcomp + q] = sum;
         }
         __syncthreads();
     }
@@ -170,11 +238,11 @@ __global__ __launch_bounds__(256) void k_coupling(const int* __restrict__ row_cl
     const int* src = colsrc + row_colptr[slot];
     const int co = cl_coef[t];
     if (kt <= 16)
-        coupling_rows<TB, TV, 16>(t, kt, ncols, S, src, Xh, Yh, co, red);
+        coupling_rows<TB, TV, 16>(kt, ncols, S, src, Xh, Yh, co, red);
     else if (kt <= 32)
-        coupling_rows<TB, TV, 32>(t, kt, ncols, S, src, Xh, Yh, co, red);
+        coupling_rows<TB, TV, 32>(kt, ncols, S, src, Xh, Yh, co, red);
     else
-        coupling_rows<TB, TV, 64>(t, kt, ncols, S, src, Xh, Yh, co, red);
+        coupling_rows<TB, TV, 64>(kt, ncols, S, src, Xh, Yh, co, red);
 }
 
 // ---------------------------------------------------------------- downward pass
@@ -218,18 +286,20 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
     const int t = leaf_id[slot];
     const int n = cl_size[t];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // wave index as a wave-uniform value: block metadata and source values then
+    // come through scalar loads, and only the block stream uses vector loads
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
     const int e = near_ptr[slot + 1];
     for (int blk = near_ptr[slot] + w; blk < e; blk += 4) {
         const int sb = near_sbeg[blk];
         const int ns = near_ssize[blk];
-        const TB* Gb = near + near_off[blk];
+        const TB* Gb = near + near_off[blk] + lane;
         const TV* us = U + (int64_t)sb * kNcomp;
         if (lane < n) {
-#pragma unroll 8
+#pragma unroll 16
             for (int j = 0; j < ns; ++j) {
-                TB gv = Gb[(int64_t)j * n + lane];
+                TB gv = ldnt(Gb + (int64_t)j * n);
                 cfma(acc0, gv, us[j * 3 + 0]);
                 cfma(acc1, gv, us[j * 3 + 1]);
                 cfma(acc2, gv, us[j * 3 + 2]);
