@@ -296,13 +296,14 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
     ncols = {c: int(size[partners[c]].sum()) for c in work}
     work.sort(key=lambda c: -int(size[c]) * ncols[c])
     # B_t is (#cols x k) per cluster; keep it in the workers when it fits
-    est_b = sum(ncols[c] * 40 * 16 for c in work)
+    est_b = sum(ncols[c] * 24 * 16 for c in work)   # B_t is #cols x k_t, k_t ~ 10-36 here
     if keep_b_bytes is None:
         keep_b_bytes = min(0.35 * _mem_available(), 120e9)
     keep_b = est_b <= keep_b_bytes
     if verbose:
         print(f"[h2gen] {geom.name}: {ncl} clusters, {part.n_far} far, {part.n_near} near, "
-              f"{nproc} workers, keep B: {keep_b} (~{est_b/1e9:.1f} GB)  {time.time()-t0:.1f}s", flush=True)
+              f"{nproc} workers, keep B: {keep_b} (~{est_b/1e9:.1f} GB of {keep_b_bytes/1e9:.0f} GB budget)  "
+              f"{time.time()-t0:.1f}s", flush=True)
 
     st = dict(tree=tree, ker=ker, partners=partners, eps=eps, eps_aca=eps_aca, keep_b=keep_b)
     _STATE.clear()

@@ -113,6 +113,37 @@ class H2Desc:
         return int(8 * ncols * (self.near.size + self.coupling.size
                                 + 2 * self.basis.size + 2 * self.transfer.size))
 
+    def save_dir(self, path: str) -> None:
+        """One .npy per array (loadable memory-mapped), plus scalars and meta as JSON."""
+        import json
+        import os
+        os.makedirs(path, exist_ok=True)
+        scal = {}
+        for k in self.__dataclass_fields__:
+            v = getattr(self, k)
+            if k == "meta":
+                continue
+            if isinstance(v, np.ndarray):
+                np.save(os.path.join(path, k + ".npy"), v)
+            else:
+                scal[k] = v
+        with open(os.path.join(path, "desc.json"), "w") as f:
+            json.dump({"scalars": scal, "meta": self.meta}, f)
+
+    @staticmethod
+    def load_dir(path: str, mmap: bool = True) -> "H2Desc":
+        import json
+        import os
+        with open(os.path.join(path, "desc.json")) as f:
+            j = json.load(f)
+        kw = dict(j["scalars"])
+        for k in H2Desc.__dataclass_fields__:
+            if k == "meta" or k in kw:
+                continue
+            kw[k] = np.load(os.path.join(path, k + ".npy"), mmap_mode="r" if mmap else None)
+        kw["meta"] = j["meta"]
+        return H2Desc(**kw)
+
     def save(self, path: str) -> None:
         arrs = {k: getattr(self, k) for k in self.__dataclass_fields__ if k != "meta"}
         arrs = {k: (np.asarray(v)) for k, v in arrs.items()}

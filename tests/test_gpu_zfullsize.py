@@ -1,0 +1,72 @@
+"""Parity at the full benchmark size: the 64^3 cube (N = 786432), eps 1e-3.
+
+The representation is built on the host (about two minutes on a 16-core host),
+then the GPU product in the configuration bench.py times is compared with the
+full oracle product on the same representation, and a GMRES(50) solve is judged
+by the oracle's FP64 residual.
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+_FULL = {}
+
+
+@pytest.fixture
+def full(capsys):
+    """Build once per session; construction progress goes to the terminal."""
+    if "op" not in _FULL:
+        import torch
+        if not torch.cuda.is_available():
+            pytest.fail("GPU tests need a GPU")
+        import h2gen
+        from h2gen.construct import build_h2
+        from paper_1703_01175_amd import H2Operator
+        with capsys.disabled():
+            print("\n[fullsize] building the 64^3 representation on the host", flush=True)
+            g = h2gen.cube(64, 4.0, (2.0, 6.0), seed=2, name="cube64")
+            d = build_h2(g, eps=1e-3, verbose=True)
+            H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0")
+        _FULL["op"] = (g, d, H)
+    return _FULL["op"]
+
+
+def test_cube64_product_matches_oracle(full, capsys):
+    import torch
+    import h2gen
+    from oracle import matvec as om
+    from oracle import precision as oprec
+    g, d, H = full
+    x = h2gen.random_vector(3 * g.n_vox, 1)
+    y = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    t0 = time.time()
+    yo = om.h2_matvec(d, x)
+    with capsys.disabled():
+        print(f"\n[fullsize] oracle product {time.time() - t0:.1f}s", flush=True)
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    assert rel <= 1e-12
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+    y32 = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
+    e32 = np.linalg.norm(y32 - yo) / np.linalg.norm(yo)
+    with capsys.disabled():
+        print(f"[fullsize] fp64 rel err {rel:.2e}, fp32 tier rel err {e32:.2e}", flush=True)
+    assert e32 <= 1e-5
+
+
+def test_cube64_gmres_residual_by_oracle(full, capsys):
+    import torch
+    import h2gen
+    from oracle import matvec as om
+    g, d, H = full
+    b = h2gen.plane_wave(g, 2)[0]
+    xs, rep = H.gmres(torch.from_numpy(b).cuda(), tol=1e-6, restart=50)
+    x = xs.cpu().numpy()
+    res = np.linalg.norm(b - om.h2_matvec(d, x)) / np.linalg.norm(b)
+    with capsys.disabled():
+        print(f"[fullsize] GMRES {rep.iterations} its, device residual {rep.rel_residual:.2e}, oracle {res:.2e}",
+              flush=True)
+    assert rep.converged and res <= 1.0001e-6
