@@ -210,6 +210,40 @@ typedef struct {
 h2_status h2_profile_enable(h2_handle h, int enable);
 h2_status h2_profile_read(h2_handle h, h2_kernel_times* out);
 
+/*
+ * Batched BF16x3 tier (representations built with tier bit 1 << H2_BF16X3).
+ *
+ * Every block product of the H^2 product becomes a complex block GEMM over
+ * W = 3 * n_rhs columns (the paper's H^2 x dense product for many right-hand
+ * sides, Sec. IV.D), done in real arithmetic on the matrix cores with each
+ * operand split into bf16 hi + lo parts (hi*hi + hi*lo + lo*hi, FP32
+ * accumulation).  Vectors are complex float (complex64), column major, ld >= N.
+ * h2_matvec with p = H2_BF16X3 runs one representation this way.
+ *
+ * A group runs several representations (geometries of any size, each with its
+ * own n_rhs) phase by phase in shared launches: leaf forward, upward levels
+ * (aligned from the leaves), couplings, downward levels (aligned from the top),
+ * near field; the launch sequence is captured in a HIP graph on first use for
+ * a given set of vector pointers, column counts and op, and replayed after.
+ * Members must outlive the group; the group buffer is caller-owned device
+ * memory of at least h2_group_plan bytes.
+ */
+typedef struct h2_group_s* h2_group;
+
+h2_status h2_group_plan(const h2_handle* members, int32_t n, size_t* dev_bytes);
+h2_status h2_group_build(const h2_handle* members, int32_t n, void* dev_buffer, size_t dev_bytes,
+                         void* stream, h2_group* out);
+/* y[i] = op(x[i]) for every member i (n_rhs[i] = 0 skips a member).  Stream ordered. */
+h2_status h2_group_matvec(h2_group g, h2_op op, const void* const* x, void* const* y, const int64_t* n_rhs,
+                          const int64_t* ld, void* stream);
+/* Autotuner: times the column tile widths 32, 64 and 128 of the block GEMM on the
+ * given vectors and keeps the fastest (written to *tile).  Synchronises. */
+h2_status h2_group_tune(h2_group g, h2_op op, const void* const* x, void* const* y, const int64_t* n_rhs,
+                        const int64_t* ld, void* stream, int32_t* tile);
+/* Set the column tile (32, 64, 128; 0 keeps it) and graph use (0 / 1). */
+h2_status h2_group_set(h2_group g, int32_t tile, int32_t use_graph);
+void h2_group_destroy(h2_group g);
+
 /* Release the handle's host metadata.  Never frees caller memory.  NULL is ignored. */
 void h2_destroy(h2_handle h);
 

@@ -86,6 +86,24 @@ def load() -> C.CDLL:
     lib.h2_gmres_solve.argtypes = [vp, vp, vp, C.POINTER(GmresOpts), C.POINTER(GmresReport), vp, sz, vp]
     lib.h2_stats.restype = C.c_int
     lib.h2_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.h2_group_plan.restype = C.c_int
+    lib.h2_group_plan.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(sz)]
+    lib.h2_group_build.restype = C.c_int
+    lib.h2_group_build.argtypes = [C.POINTER(vp), C.c_int32, vp, sz, vp, C.POINTER(vp)]
+    lib.h2_group_matvec.restype = C.c_int
+    lib.h2_group_matvec.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64), vp]
+    lib.h2_group_tune.restype = C.c_int
+    lib.h2_group_tune.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64), vp, C.POINTER(C.c_int32)]
+    lib.h2_group_set.restype = C.c_int
+    lib.h2_group_set.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.h2_group_destroy.restype = None
+    lib.h2_group_destroy.argtypes = [vp]
+    lib.h2_profile_enable.restype = C.c_int
+    lib.h2_profile_enable.argtypes = [vp, C.c_int]
+    lib.h2_profile_read.restype = C.c_int
+    lib.h2_profile_read.argtypes = [vp, vp]
     lib.h2_destroy.restype = None
     lib.h2_destroy.argtypes = [vp]
     _LIB = lib

@@ -104,3 +104,77 @@ class H2Operator:
             self.close()
         except Exception:
             pass
+
+
+class H2Group:
+    """Several operators (built with the "bf16x3" tier) applied together: every phase of
+    the product runs as one launch over all members, replayed from a HIP graph."""
+
+    def __init__(self, ops, stream=None):
+        import torch
+        self.ops = list(ops)
+        self.lib = _lib.load()
+        n = len(self.ops)
+        arr = (C.c_void_p * n)(*[o.handle.value for o in self.ops])
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.h2_group_plan(arr, n, C.byref(nbytes)))
+        self.buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.ops[0].device)
+        g = C.c_void_p(0)
+        _lib.check(self.lib.h2_group_build(arr, n, C.c_void_p(self.buf.data_ptr()), nbytes, _stream_ptr(stream),
+                                           C.byref(g)))
+        self.handle = g
+
+    def _args(self, xs, ys):
+        import torch
+        n = len(self.ops)
+        if len(xs) != n or len(ys) != n:
+            raise ValueError("one input and one output per member")
+        xp = (C.c_void_p * n)()
+        yp = (C.c_void_p * n)()
+        nr = (C.c_int64 * n)()
+        ld = (C.c_int64 * n)()
+        for i, (o, x, y) in enumerate(zip(self.ops, xs, ys)):
+            if x is None:
+                nr[i] = 0
+                ld[i] = o.N
+                continue
+            if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous() or x.shape[-1] != o.N:
+                raise ValueError("member vectors must be contiguous complex64 CUDA tensors of length N")
+            xp[i] = x.data_ptr()
+            yp[i] = y.data_ptr()
+            nr[i] = 1 if x.dim() == 1 else int(x.shape[0])
+            ld[i] = o.N
+        return xp, yp, nr, ld
+
+    def matvec(self, xs, op: str = "Z", outs=None, stream=None):
+        import torch
+        if outs is None:
+            outs = [None if x is None else torch.empty_like(x) for x in xs]
+        xp, yp, nr, ld = self._args(xs, outs)
+        _lib.check(self.lib.h2_group_matvec(self.handle, _lib.OP[op], xp, yp, nr, ld, _stream_ptr(stream)))
+        return outs
+
+    def tune(self, xs, op: str = "Z", outs=None, stream=None) -> int:
+        import torch
+        if outs is None:
+            outs = [None if x is None else torch.empty_like(x) for x in xs]
+        xp, yp, nr, ld = self._args(xs, outs)
+        tile = C.c_int32(0)
+        _lib.check(self.lib.h2_group_tune(self.handle, _lib.OP[op], xp, yp, nr, ld, _stream_ptr(stream),
+                                          C.byref(tile)))
+        return int(tile.value)
+
+    def set(self, tile: int = 0, graph: bool = True):
+        _lib.check(self.lib.h2_group_set(self.handle, int(tile), int(graph)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.h2_group_destroy(self.handle)
+            self.handle = C.c_void_p(0)
+            self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

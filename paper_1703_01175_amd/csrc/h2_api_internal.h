@@ -7,6 +7,9 @@
 
 #include "../../include/h2vie.h"
 #include "h2_internal.h"
+#include "h2_batch.h"
+
+#include <vector>
 
 namespace h2 {
 
@@ -29,4 +32,76 @@ void* handle_aux(h2_handle h, size_t* bytes);
 bool handle_live(h2_handle h);
 h2_status handle_fail(h2_status st, const char* msg);
 
+// Batched BF16x3 tier (h2_batch_api.cpp)
+h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B);
+size_t group_need(const h2_handle* hs, int n);
+size_t group_need_batch(BatchHost* B);
+h2_status group_create(const h2_handle* hs, int n, void* mem, size_t bytes, hipStream_t s, h2_group* out);
+h2_status group_run(h2_group g, int op, const void* const* x, void* const* y, const int64_t* n_rhs,
+                    const int64_t* ld, hipStream_t s);
+void group_destroy(h2_group g);
+
+// Event pairs around kernel families; read back (and summed) on demand.
+struct EventProfiler : Profiler {
+    struct Rec { int family; hipEvent_t a, b; };
+    std::vector<Rec> open, done;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int family, hipStream_t s) override {
+        hipEvent_t a = take();
+        if (!a) return;
+        (void)hipEventRecord(a, s);
+        open.push_back({family, a, nullptr});
+    }
+    void end(int family, hipStream_t s) override {
+        for (size_t i = open.size(); i-- > 0;)
+            if (open[i].family == family && open[i].b == nullptr) {
+                hipEvent_t b = take();
+                if (!b) return;
+                (void)hipEventRecord(b, s);
+                open[i].b = b;
+                done.push_back(open[i]);
+                open.erase(open.begin() + i);
+                return;
+            }
+    }
+    ~EventProfiler() override {
+        for (auto& r : done) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto& r : open) (void)hipEventDestroy(r.a);
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+
+constexpr uint32_t kHandleMagic = 0x48325649u;  // "H2VI"
+
 }  // namespace h2
+
+struct h2_handle_s {
+    uint32_t magic = h2::kHandleMagic;
+    h2::DevH2 dev;
+    h2::LevelLaunch lv;
+    h2_stats_t stats{};
+    char* base = nullptr;
+    size_t bytes = 0;
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
+    int tiers = 1;
+    h2::EventProfiler* prof = nullptr;
+    h2::BatchHost* batch = nullptr;     // BF16x3 batched tier (tier bit 2)
+    h2_group self_group = nullptr;      // the handle alone, for h2_matvec with BF16X3
+    ~h2_handle_s() {
+        if (self_group) h2::group_destroy(self_group);
+        delete batch;
+        delete prof;
+    }
+};

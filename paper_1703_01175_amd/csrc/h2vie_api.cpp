@@ -34,7 +34,6 @@ h2_status fail(h2_status st, const char* fmt, ...) {
     return st;
 }
 
-constexpr uint32_t kMagic = 0x48325649u;  // "H2VI"
 
 // Planned layout: every array at a 256-byte aligned offset of the device buffer.
 struct Layout {
@@ -62,7 +61,11 @@ struct Plan {
     size_t o_perm, o_chi, o_cl[7], o_toff, o_boff, o_leaf, o_nptr, o_nsb, o_nss, o_noff;
     size_t o_rowcl, o_rownc, o_rowcp, o_colsrc, o_rowoff, o_up, o_down;
     size_t o_data[3][4];      // tier x {near, coupling, basis, transfer}
-    size_t o_data_lo[4];      // BF16 low parts
+    // batched BF16x3 tier
+    BatchHost* batch = nullptr;
+    size_t o_arena = 0, o_ub = 0, o_xb = 0, o_yhb = 0, o_xf = 0, o_yhf = 0, o_yf = 0, o_prow = 0, o_jobs = 0, o_group = 0;
+    size_t group_bytes = 0;
+    ~Plan() { delete batch; }
     size_t o_U, o_X, o_Y, o_aux;
     size_t aux_bytes = 0;
     Layout lay;
@@ -306,8 +309,22 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     if (P.tiers & 2)
         for (int q = 0; q < 4; ++q) P.o_data[1][q] = L.add(std::max<int64_t>(lens[q], 1) * 8);
     if (P.tiers & 4) {
-        for (int q = 0; q < 4; ++q) P.o_data[2][q] = L.add(std::max<int64_t>(lens[q], 1) * 4);
-        for (int q = 0; q < 4; ++q) P.o_data_lo[q] = L.add(std::max<int64_t>(lens[q], 1) * 4);
+        P.batch = new BatchHost();
+        BatchHost& B = *P.batch;
+        h2_status bs = plan_batch(d, o->max_rhs, B);
+        if (bs != H2_OK) return fail(bs, "batched tier needs ranks <= 64 and fewer than 2^31 padded rows");
+        const size_t cols = size_t(B.max_cols);
+        P.o_arena = L.add(size_t(std::max<int64_t>(B.arena_elems, 1)) * 2);
+        P.o_ub = L.add(4 * size_t(B.urows) * cols * 2);
+        P.o_xb = L.add(4 * size_t(B.crows) * cols * 2);
+        P.o_yhb = L.add(4 * size_t(B.crows) * cols * 2);
+        P.o_xf = L.add(2 * size_t(B.crows) * cols * 4);
+        P.o_yhf = L.add(2 * size_t(B.crows) * cols * 4);
+        P.o_yf = L.add(2 * size_t(B.urows) * cols * 4);
+        P.o_prow = L.add(size_t(n) * 4);
+        P.o_jobs = L.add(std::max<size_t>(B.jobs.size(), 1) * sizeof(PackJob));
+        P.group_bytes = group_need_batch(&B);
+        P.o_group = L.add(P.group_bytes);
     }
     const size_t cols = size_t(kNcomp);
     P.o_U = L.add(size_t(n) * cols * 16);
@@ -318,61 +335,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     return H2_OK;
 }
 
-// Event pairs around kernel families; read back (and summed) on demand.
-struct EventProfiler : Profiler {
-    struct Rec { int family; hipEvent_t a, b; };
-    std::vector<Rec> open, done;
-    std::vector<hipEvent_t> pool;
-    hipEvent_t take() {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    void begin(int family, hipStream_t s) override {
-        hipEvent_t a = take();
-        if (!a) return;
-        (void)hipEventRecord(a, s);
-        open.push_back({family, a, nullptr});
-    }
-    void end(int family, hipStream_t s) override {
-        for (size_t i = open.size(); i-- > 0;)
-            if (open[i].family == family && open[i].b == nullptr) {
-                hipEvent_t b = take();
-                if (!b) return;
-                (void)hipEventRecord(b, s);
-                open[i].b = b;
-                done.push_back(open[i]);
-                open.erase(open.begin() + i);
-                return;
-            }
-    }
-    ~EventProfiler() override {
-        for (auto& r : done) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
-        for (auto& r : open) (void)hipEventDestroy(r.a);
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
 }  // namespace
-
-struct h2_handle_s {
-    uint32_t magic = kMagic;
-    DevH2 dev;
-    LevelLaunch lv;
-    h2_stats_t stats{};
-    char* base = nullptr;
-    size_t bytes = 0;
-    void* aux = nullptr;
-    size_t aux_bytes = 0;
-    int tiers = 1;
-    EventProfiler* prof = nullptr;
-    ~h2_handle_s() { delete prof; }
-};
 
 // Live handles: a destroyed or foreign pointer is rejected before it is read.
 static std::mutex g_handles_mu;
@@ -381,7 +344,7 @@ static std::set<h2_handle> g_handles;
 static bool handle_ok(h2_handle h) {
     if (h == nullptr) return false;
     std::lock_guard<std::mutex> lk(g_handles_mu);
-    return g_handles.count(h) != 0 && h->magic == kMagic;
+    return g_handles.count(h) != 0 && h->magic == kHandleMagic;
 }
 
 extern "C" {
@@ -446,11 +409,6 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
             hipError_t e = launch_convert_fp32((const double2*)(base + P.o_data[0][q]), (float2*)(base + P.o_data[1][q]), lens[q], s);
             if (e != hipSuccess) return fail(H2_ERR_DEVICE, "fp32 conversion failed: %s", hipGetErrorString(e));
         }
-        if (P.tiers & 4) {
-            hipError_t e = launch_split_bf16((const double2*)(base + P.o_data[0][q]), (uint32_t*)(base + P.o_data[2][q]),
-                                             (uint32_t*)(base + P.o_data_lo[q]), lens[q], s);
-            if (e != hipSuccess) return fail(H2_ERR_DEVICE, "bf16 split failed: %s", hipGetErrorString(e));
-        }
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "build synchronisation failed: %s", hipGetErrorString(e));
@@ -491,17 +449,43 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.down_list = (const int*)(base + P.o_down);
     for (int tier = 0; tier < 3; ++tier) {
         D.has_tier[tier] = (P.tiers >> tier) & 1;
-        if (!D.has_tier[tier]) continue;
+        if (!D.has_tier[tier] || tier == 2) continue;
         D.tier[tier].near = base + P.o_data[tier][0];
         D.tier[tier].coupling = base + P.o_data[tier][1];
         D.tier[tier].basis = base + P.o_data[tier][2];
         D.tier[tier].transfer = base + P.o_data[tier][3];
     }
     if (P.tiers & 4) {
-        D.tier[2].near_lo = base + P.o_data_lo[0];
-        D.tier[2].coupling_lo = base + P.o_data_lo[1];
-        D.tier[2].basis_lo = base + P.o_data_lo[2];
-        D.tier[2].transfer_lo = base + P.o_data_lo[3];
+        BatchHost* B = P.batch;
+        P.batch = nullptr;
+        h->batch = B;
+        B->arena = (uint16_t*)(base + P.o_arena);
+        B->Ub = (uint16_t*)(base + P.o_ub);
+        B->Xb = (uint16_t*)(base + P.o_xb);
+        B->Yhb = (uint16_t*)(base + P.o_yhb);
+        B->Xf = (float*)(base + P.o_xf);
+        B->Yhf = (float*)(base + P.o_yhf);
+        B->Yf = (float*)(base + P.o_yf);
+        B->prow_dev = (int*)(base + P.o_prow);
+        const size_t cols = size_t(B->max_cols);
+        hipError_t e2 = hipMemcpyAsync(B->prow_dev, B->prow.data(), B->prow.size() * 4, hipMemcpyHostToDevice, s);
+        if (e2 == hipSuccess && !B->jobs.empty())
+            e2 = hipMemcpyAsync(base + P.o_jobs, B->jobs.data(), B->jobs.size() * sizeof(PackJob), hipMemcpyHostToDevice, s);
+        // bf16 vector planes start at zero (their padding rows stay zero)
+        if (e2 == hipSuccess) e2 = launch_fill_u16(B->Ub, 4 * int64_t(B->urows) * int64_t(cols), s);
+        if (e2 == hipSuccess) e2 = launch_fill_u16(B->Xb, 4 * int64_t(B->crows) * int64_t(cols), s);
+        if (e2 == hipSuccess) e2 = launch_fill_u16(B->Yhb, 4 * int64_t(B->crows) * int64_t(cols), s);
+        const double2* srcs[4] = {(const double2*)(base + P.o_data[0][0]), (const double2*)(base + P.o_data[0][1]),
+                                  (const double2*)(base + P.o_data[0][2]), (const double2*)(base + P.o_data[0][3])};
+        if (e2 == hipSuccess)
+            e2 = launch_pack((const PackJob*)(base + P.o_jobs), int(B->jobs.size()), srcs, B->arena, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        B->jobs.clear();
+        B->jobs.shrink_to_fit();
+        if (e2 != hipSuccess) {
+            delete h;
+            return fail(H2_ERR_DEVICE, "batched tier packing failed: %s", hipGetErrorString(e2));
+        }
     }
     D.U = base + P.o_U;
     D.Xh = base + P.o_X;
@@ -535,6 +519,13 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         std::lock_guard<std::mutex> lk(g_handles_mu);
         g_handles.insert(h);
     }
+    if (h->batch) {
+        h2_status gs = group_create(&h, 1, base + P.o_group, P.group_bytes, s, &h->self_group);
+        if (gs != H2_OK) {
+            h2_destroy(h);
+            return gs;
+        }
+    }
     *out = h;
     return H2_OK;
 }
@@ -556,6 +547,12 @@ h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* 
     const char* yb = (const char*)y;
     const size_t span = size_t((n_rhs - 1) * ld + N) * esz;
     if (xb < yb + span && yb < xb + span) return fail(H2_ERR_INVALID_ARG, "x and y overlap");
+    if (p == H2_BF16X3) {
+        const void* xs[1] = {x};
+        void* ys[1] = {y};
+        const int64_t nr[1] = {n_rhs}, lds[1] = {ld};
+        return group_run(h->self_group, int(op), xs, ys, nr, lds, reinterpret_cast<hipStream_t>(stream));
+    }
     hipError_t e = launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld, reinterpret_cast<hipStream_t>(stream),
                                  h->prof);
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "matvec launch failed: %s", hipGetErrorString(e));
