@@ -143,6 +143,8 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
 h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* y, int64_t n_rhs,
                     int64_t ld, void* stream);
 
+typedef enum { H2_PRECOND_NONE = 0, H2_PRECOND_BLOCKDIAG = 1, H2_PRECOND_MLP = 2 } h2_precond;
+
 typedef struct {
     int32_t restart;        /* Krylov dimension m per cycle (1..128); 50 */
     int32_t max_matvec;     /* budget of products with Z */
@@ -150,6 +152,8 @@ typedef struct {
     int32_t precision;      /* h2_precision of the inner products (FP64 = plain GMRES) */
     double inner_tol;       /* inner tolerance of refinement when precision != FP64 */
     int32_t max_outer;      /* refinement steps when precision != FP64 */
+    int32_t precond;        /* h2_precond: right preconditioner (flexible GMRES when not NONE) */
+    int32_t use_x0;         /* 1: x holds the initial guess on entry (resume); 0: x0 = 0 */
 } h2_gmres_opts;
 
 typedef struct {
@@ -164,13 +168,18 @@ typedef struct {
 /* Workspace bytes for h2_gmres_solve with opts o (device memory, caller owned). */
 h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes);
 
-/* Solve Z x = b for one right-hand side by restarted GMRES(m) with x0 = 0:
+/* Solve Z x = b for one right-hand side by restarted GMRES(m) from x0 = 0 (or
+ * the given x with use_x0 = 1; restarting from a saved iterate resumes a solve):
  * Arnoldi by classical Gram-Schmidt applied twice, Givens rotations on the
  * Hessenberg matrix, all on the device in FP64; the true residual b - Z x is
  * formed after every cycle and decides convergence.  With precision FP32 or
  * BF16X3 the solve is iterative refinement: r = b - Z x in FP64, an inner
  * GMRES in FP64 arithmetic whose products use the lower-precision blocks,
- * x += d.  b, x: device complex double, length N.  Synchronises the stream.
+ * x += d.  With a preconditioner P the method is flexible GMRES with right
+ * preconditioning: z_j = P(v_j) is stored, w = Z z_j, and x += sum y_j z_j, so P may
+ * change between steps (the MLP is nonlinear).  PRECOND_BLOCKDIAG needs
+ * h2_precond_blockdiag, PRECOND_MLP needs h2_precond_mlp, both first.
+ * b, x: device complex double, length N.  Synchronises the stream.
  * Returns OK, NOT_CONVERGED (x holds the last iterate) or an error. */
 h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o,
                          h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
@@ -186,6 +195,63 @@ typedef struct {
 } h2_stats_t;
 
 h2_status h2_stats(h2_handle h, h2_stats_t* out);
+
+/*
+ * Per-leaf preconditioners.
+ *
+ * Block diagonal: z_t = (Z_tt)^-1 r_t per leaf t, Z_tt = I + sigma k^2 V G_tt diag(chi_t)
+ * on each component; the inverses are formed on the device (Gauss-Jordan with
+ * partial pivoting on [Z_tt | I]) into a caller buffer of h2_precond_blockdiag_bytes.
+ *
+ * Learned: one MLP shared by all leaves (two hidden ReLU layers; bf16 weights,
+ * FP32 master weights and accumulation).  A leaf's input is
+ * x = [Re r_t / s, Im r_t / s, Re chi_t] (unknowns 3i + c of the leaf's voxels in
+ * tree order, zero padded to n_pad voxels: n_in = 7 n_pad), its output
+ * y = [Re z_t, Im z_t] / s (n_out = 6 n_pad), s = ||r|| / sqrt(N).
+ * Parameter block (device, caller owned, h2_mlp_sizes bytes): FP32 master weights
+ * W1 (n_hidden x n_in, row major), b1, W2, b2, W3 (n_out x n_hidden), b3; then the
+ * Adam moments m and v; then the bf16 copy used by the passes.
+ */
+typedef struct { int32_t n_in, n_hidden, n_out; } h2_mlp_dims;
+
+h2_status h2_mlp_sizes(const h2_mlp_dims* dims, int64_t batch, size_t* param_bytes, size_t* work_bytes);
+/* Upload master weights (host, float32, the layout above), zero the Adam moments. */
+h2_status h2_mlp_set(const h2_mlp_dims* dims, void* params, const float* master_host, void* stream);
+h2_status h2_mlp_get(const h2_mlp_dims* dims, const void* params, float* master_host, void* stream);
+/* Y (n x n_out) = MLP(X (n x n_in)), device row-major float32. */
+h2_status h2_mlp_forward(const h2_mlp_dims* dims, void* params, const float* X, float* Y, int64_t n, void* work,
+                         size_t work_bytes, void* stream);
+/* Gradients (master layout, device) and loss 0.5/n sum ||Y - T||^2 (device float). */
+h2_status h2_mlp_grad(const h2_mlp_dims* dims, void* params, const float* X, const float* T, int64_t n, float* grad,
+                      float* loss, void* work, size_t work_bytes, void* stream);
+/* Adam (beta 0.9, 0.999, eps 1e-8) over minibatches: epoch e visits rows
+ * order[e n .. e n + n) (device int32, caller-drawn permutations) in slices of
+ * `batch`; epoch_loss_host (optional, epochs floats) receives mean minibatch losses. */
+h2_status h2_mlp_train(const h2_mlp_dims* dims, void* params, const float* X, const float* T, int64_t n,
+                       const int* order, int32_t epochs, int32_t batch, float lr, float* epoch_loss_host, void* work,
+                       size_t work_bytes, void* stream);
+
+h2_status h2_leaf_count(h2_handle h, int32_t* n_leaves, int32_t* max_leaf);
+/* Features (n_leaves x 7 n_pad) of a residual r (device complex double, length N);
+ * leaves in cluster order.  scratch: 64 bytes of device memory. */
+h2_status h2_leaf_features(h2_handle h, int32_t n_pad, const void* r, float* X, void* scratch, void* stream);
+/* Targets (n_leaves x 6 n_pad) [Re e_t, Im e_t] / s with s from ||r|| (same scaling as the features). */
+h2_status h2_leaf_targets(h2_handle h, int32_t n_pad, const void* e, const void* r, float* T, void* scratch,
+                          void* stream);
+h2_status h2_precond_blockdiag_bytes(h2_handle h, size_t* bytes);
+/* Form the leaf inverses into buf; INVALID_ARG if a leaf block is singular. Synchronises. */
+h2_status h2_precond_blockdiag(h2_handle h, void* buf, size_t bytes, void* stream);
+/* Attach an MLP (parameters stay caller owned) for PRECOND_MLP solves.  base:
+ * PRECOND_NONE (z = MLP output) or PRECOND_BLOCKDIAG (z = block-diagonal solve
+ * plus the MLP output, a learned correction on top of the fallback; needs
+ * h2_precond_blockdiag first). */
+h2_status h2_precond_mlp(h2_handle h, const h2_mlp_dims* dims, int32_t n_pad, void* params, int32_t base);
+/* z = P(r) once, outside a solve (r, z: distinct device complex double vectors of
+ * length N, caller order); work: device memory of h2_precond_apply_bytes (0 for
+ * BLOCKDIAG).  Asynchronous on the stream. */
+h2_status h2_precond_apply_bytes(h2_handle h, int32_t precond, size_t* bytes);
+h2_status h2_precond_apply(h2_handle h, int32_t precond, const void* r, void* z, void* work, size_t work_bytes,
+                           void* stream);
 
 /* Kernel families of the product, in launch order. */
 enum {

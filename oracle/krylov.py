@@ -52,8 +52,8 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
     n = b.shape[0]
     bnorm = float(np.linalg.norm(b))
     x = np.zeros(n, np.complex128) if x0 is None else np.array(x0, np.complex128)
-    if bnorm == 0.0:
-        return x, SolveReport(True, 0, 0, 0, 0.0)
+    if bnorm == 0.0:      # the unique solution of A x = 0 (A nonsingular) is x = 0, whatever x0 was
+        return np.zeros(n, np.complex128), SolveReport(True, 0, 0, 0, 0.0)
     mv = 0
     its = 0
     restarts = 0

@@ -44,7 +44,15 @@ class BuildOpts(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_matvec", C.c_int32), ("tol", C.c_double),
-                ("precision", C.c_int32), ("inner_tol", C.c_double), ("max_outer", C.c_int32)]
+                ("precision", C.c_int32), ("inner_tol", C.c_double), ("max_outer", C.c_int32),
+                ("precond", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class MlpDims(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32)]
+
+
+PRECOND = {"none": 0, "blockdiag": 1, "mlp": 2}
 
 
 class GmresReport(C.Structure):
@@ -104,6 +112,26 @@ def load() -> C.CDLL:
     lib.h2_profile_enable.argtypes = [vp, C.c_int]
     lib.h2_profile_read.restype = C.c_int
     lib.h2_profile_read.argtypes = [vp, vp]
+    pd = C.POINTER(MlpDims)
+    for name, args in [
+        ("h2_mlp_sizes", [pd, C.c_int64, C.POINTER(sz), C.POINTER(sz)]),
+        ("h2_mlp_set", [pd, vp, vp, vp]),
+        ("h2_mlp_get", [pd, vp, vp, vp]),
+        ("h2_mlp_forward", [pd, vp, vp, vp, C.c_int64, vp, sz, vp]),
+        ("h2_mlp_grad", [pd, vp, vp, vp, C.c_int64, vp, vp, vp, sz, vp]),
+        ("h2_mlp_train", [pd, vp, vp, vp, C.c_int64, vp, C.c_int32, C.c_int32, C.c_float, vp, vp, sz, vp]),
+        ("h2_leaf_count", [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        ("h2_leaf_features", [vp, C.c_int32, vp, vp, vp, vp]),
+        ("h2_leaf_targets", [vp, C.c_int32, vp, vp, vp, vp, vp]),
+        ("h2_precond_blockdiag_bytes", [vp, C.POINTER(sz)]),
+        ("h2_precond_blockdiag", [vp, vp, sz, vp]),
+        ("h2_precond_mlp", [vp, pd, C.c_int32, vp, C.c_int32]),
+        ("h2_precond_apply_bytes", [vp, C.c_int32, C.POINTER(sz)]),
+        ("h2_precond_apply", [vp, C.c_int32, vp, vp, vp, sz, vp]),
+    ]:
+        f = getattr(lib, name)
+        f.restype = C.c_int
+        f.argtypes = args
     lib.h2_destroy.restype = None
     lib.h2_destroy.argtypes = [vp]
     _LIB = lib

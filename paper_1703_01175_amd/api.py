@@ -69,14 +69,20 @@ class H2Operator:
 
     # ------------------------------------------------------------------ solver
     def gmres(self, b, x=None, tol: float = 1e-6, restart: int = 50, max_matvec: int = 10000,
-              precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 30, stream=None):
+              precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 30, precond: str = "none",
+              x0=None, stream=None):
+        """Solve Z x = b (x0 = 0, or resume from x0); precond "blockdiag"/"mlp" gives flexible GMRES."""
         import torch
         if b.dtype != torch.complex128 or not b.is_cuda or b.shape != (self.N,):
             raise ValueError("b must be a complex128 CUDA tensor of length N")
         if x is None:
             x = torch.empty_like(b)
+        use_x0 = 0
+        if x0 is not None:
+            x.copy_(x0)
+            use_x0 = 1
         opts = _lib.GmresOpts(restart=restart, max_matvec=max_matvec, tol=tol, precision=_lib.PRECISION[precision],
-                              inner_tol=inner_tol, max_outer=max_outer)
+                              inner_tol=inner_tol, max_outer=max_outer, precond=_lib.PRECOND[precond], use_x0=use_x0)
         nbytes = C.c_size_t(0)
         _lib.check(self.lib.h2_gmres_workspace(self.handle, C.byref(opts), C.byref(nbytes)))
         work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
@@ -86,6 +92,59 @@ class H2Operator:
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
                               rep.rel_residual)
+
+    # ------------------------------------------------------------------ per-leaf preconditioners
+    def leaf_count(self):
+        n, m = C.c_int32(0), C.c_int32(0)
+        _lib.check(self.lib.h2_leaf_count(self.handle, C.byref(n), C.byref(m)))
+        return int(n.value), int(m.value)
+
+    def features(self, r, n_pad: int, stream=None):
+        """(n_leaves, 7 n_pad) float32 features of a residual r (complex128, length N)."""
+        import torch
+        nl, _ = self.leaf_count()
+        X = torch.empty((nl, 7 * n_pad), dtype=torch.float32, device=self.device)
+        scratch = torch.empty(64, dtype=torch.uint8, device=self.device)
+        _lib.check(self.lib.h2_leaf_features(self.handle, n_pad, C.c_void_p(r.data_ptr()), C.c_void_p(X.data_ptr()),
+                                             C.c_void_p(scratch.data_ptr()), _stream_ptr(stream)))
+        return X
+
+    def targets(self, e, r, n_pad: int, stream=None):
+        """(n_leaves, 6 n_pad) float32 targets [Re e_t, Im e_t] / s, s from ||r||."""
+        import torch
+        nl, _ = self.leaf_count()
+        T = torch.empty((nl, 6 * n_pad), dtype=torch.float32, device=self.device)
+        scratch = torch.empty(64, dtype=torch.uint8, device=self.device)
+        _lib.check(self.lib.h2_leaf_targets(self.handle, n_pad, C.c_void_p(e.data_ptr()), C.c_void_p(r.data_ptr()),
+                                            C.c_void_p(T.data_ptr()), C.c_void_p(scratch.data_ptr()),
+                                            _stream_ptr(stream)))
+        return T
+
+    def precond_blockdiag(self, stream=None):
+        import torch
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.h2_precond_blockdiag_bytes(self.handle, C.byref(nbytes)))
+        self.bd_buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _lib.check(self.lib.h2_precond_blockdiag(self.handle, C.c_void_p(self.bd_buf.data_ptr()), nbytes,
+                                                 _stream_ptr(stream)))
+
+    def precond_apply(self, r, which: str = "blockdiag", stream=None):
+        """z = P(r) with an attached preconditioner (complex128 device vectors)."""
+        import torch
+        pc = _lib.PRECOND[which]
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.h2_precond_apply_bytes(self.handle, pc, C.byref(nbytes)))
+        work = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
+        z = torch.empty_like(r)
+        _lib.check(self.lib.h2_precond_apply(self.handle, pc, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()),
+                                             C.c_void_p(work.data_ptr()), nbytes, _stream_ptr(stream)))
+        return z
+
+    def attach_mlp(self, mlp, base: str = "none"):
+        """Use `mlp` for precond="mlp"; base "blockdiag" adds its output to the block-diagonal solve."""
+        _lib.check(self.lib.h2_precond_mlp(self.handle, C.byref(mlp.dims), mlp.n_pad, C.c_void_p(mlp.params.data_ptr()),
+                                           _lib.PRECOND[base]))
+        self.mlp = mlp
 
     # ------------------------------------------------------------------ misc
     def stats(self) -> dict:
@@ -178,3 +237,88 @@ class H2Group:
             self.close()
         except Exception:
             pass
+
+
+class LeafMLP:
+    """The per-leaf MLP: parameters and workspaces in device memory, passes in the library."""
+
+    def __init__(self, n_pad: int, hidden: int = 256, seed: int = 0, batch: int = 512, device: str = "cuda",
+                 zero_output: bool = False):
+        """zero_output: start with a zero last layer (output 0), for a correction on top of another map."""
+        import numpy as np
+        import torch
+        self.lib = _lib.load()
+        self.n_pad = int(n_pad)
+        self.dims = _lib.MlpDims(7 * n_pad, hidden, 6 * n_pad)
+        self.device = torch.device(device)
+        pb, wb = C.c_size_t(0), C.c_size_t(0)
+        _lib.check(self.lib.h2_mlp_sizes(C.byref(self.dims), batch, C.byref(pb), C.byref(wb)))
+        self.params = torch.empty(int(pb.value), dtype=torch.uint8, device=self.device)
+        self.batch = batch
+        self.nmaster = hidden * 7 * n_pad + hidden + hidden * hidden + hidden + 6 * n_pad * hidden + 6 * n_pad
+        # He-normal initial weights drawn here (seeded) and handed to the library
+        rng = np.random.default_rng(seed)
+        n_in, h, n_out = 7 * n_pad, hidden, 6 * n_pad
+        parts = [rng.standard_normal(h * n_in) * np.sqrt(2.0 / n_in), np.zeros(h),
+                 rng.standard_normal(h * h) * np.sqrt(2.0 / h), np.zeros(h),
+                 rng.standard_normal(n_out * h) * np.sqrt(1.0 / h) * (0.0 if zero_output else 1.0), np.zeros(n_out)]
+        self.set_master(np.concatenate(parts).astype(np.float32))
+
+    def _work(self, n):
+        import torch
+        wb = C.c_size_t(0)
+        _lib.check(self.lib.h2_mlp_sizes(C.byref(self.dims), max(int(n), 1), None, C.byref(wb)))
+        return torch.empty(int(wb.value), dtype=torch.uint8, device=self.device), wb
+
+    def set_master(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.nmaster
+        _lib.check(self.lib.h2_mlp_set(C.byref(self.dims), C.c_void_p(self.params.data_ptr()),
+                                       C.c_void_p(w.ctypes.data), None))
+
+    def master(self):
+        import numpy as np
+        w = np.empty(self.nmaster, np.float32)
+        _lib.check(self.lib.h2_mlp_get(C.byref(self.dims), C.c_void_p(self.params.data_ptr()),
+                                       C.c_void_p(w.ctypes.data), None))
+        return w
+
+    def forward(self, X):
+        import torch
+        n = X.shape[0]
+        Y = torch.empty((n, self.dims.n_out), dtype=torch.float32, device=self.device)
+        work, wb = self._work(n)
+        _lib.check(self.lib.h2_mlp_forward(C.byref(self.dims), C.c_void_p(self.params.data_ptr()),
+                                           C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), n,
+                                           C.c_void_p(work.data_ptr()), wb, _stream_ptr()))
+        return Y
+
+    def grad(self, X, T):
+        import torch
+        n = X.shape[0]
+        g = torch.empty(self.nmaster, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        work, wb = self._work(n)
+        _lib.check(self.lib.h2_mlp_grad(C.byref(self.dims), C.c_void_p(self.params.data_ptr()),
+                                        C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                        C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                        C.c_void_p(work.data_ptr()), wb, _stream_ptr()))
+        return g, loss
+
+    def train(self, X, T, epochs: int = 20, batch: int = 256, lr: float = 1e-3, seed: int = 0):
+        """Adam over seeded minibatch permutations (drawn here, handed to the library)."""
+        import numpy as np
+        import torch
+        n = X.shape[0]
+        rng = np.random.default_rng(seed)
+        order = np.concatenate([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+        order_d = torch.from_numpy(order).to(self.device)
+        work, wb = self._work(batch)
+        losses = np.zeros(epochs, np.float32)
+        _lib.check(self.lib.h2_mlp_train(C.byref(self.dims), C.c_void_p(self.params.data_ptr()),
+                                         C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                         C.c_void_p(order_d.data_ptr()), epochs, batch, float(lr),
+                                         C.c_void_p(losses.ctypes.data), C.c_void_p(work.data_ptr()), wb,
+                                         _stream_ptr()))
+        return losses

@@ -25,6 +25,14 @@ hipError_t launch_split_bf16(const double2* src, uint32_t* hi, uint32_t* lo, int
 hipError_t launch_vec_to_fp32(const double2* src, float2* dst, int64_t n, hipStream_t s);
 hipError_t launch_vec_to_fp64(const float2* src, double2* dst, int64_t n, hipStream_t s);
 
+// Preconditioner applications (h2_learn.hip).
+hipError_t launch_bd_apply(const LeafInfo& li, const int* perm, const double2* inv, const double2* r, double2* z,
+                           hipStream_t s);
+// MLP correction z = MLP(r) per leaf; X, H1, H2, Y: activations of n_leaves rows; norm: 1 double
+hipError_t mlp_apply_handle(h2_handle h, const double2* r, double2* z, float* X, float* H1, float* H2, float* Y,
+                            double* norm, hipStream_t s);
+size_t mlp_apply_work_bytes(h2_handle h);
+
 // Handle accessors (h2vie_api.cpp) for the solver translation unit.
 const DevH2* handle_dev(h2_handle h);
 const LevelLaunch* handle_levels(h2_handle h);
@@ -99,6 +107,13 @@ struct h2_handle_s {
     h2::EventProfiler* prof = nullptr;
     h2::BatchHost* batch = nullptr;     // BF16x3 batched tier (tier bit 2)
     h2_group self_group = nullptr;      // the handle alone, for h2_matvec with BF16X3
+    // preconditioners
+    void* bd_buf = nullptr;             // [M_t | I] after elimination, per leaf (caller memory)
+    bool bd_ready = false;
+    void* mlp_params = nullptr;         // MLP parameter block (caller memory)
+    h2_mlp_dims mlp_dims{0, 0, 0};
+    int mlp_npad = 0;
+    int mlp_base = 0;                   // H2_PRECOND_NONE, or BLOCKDIAG: z = BD(r) + MLP correction
     ~h2_handle_s() {
         if (self_group) h2::group_destroy(self_group);
         delete batch;

@@ -24,6 +24,17 @@ struct TierData {
     const void* transfer_lo = nullptr;
 };
 
+// Leaves in cluster order, for the per-leaf preconditioners.
+struct LeafInfo {
+    int n = 0;                        // number of leaves
+    const int* beg = nullptr;         // first tree position
+    const int* size = nullptr;        // voxels
+    const int64_t* diag = nullptr;    // complex offset of the diagonal near block G_tt
+    const int64_t* inv_off = nullptr; // complex offset of [M_t | I] in the block-diagonal buffer
+    int64_t inv_elems = 0;            // total complex elements of that buffer
+    int max_leaf = 0;
+};
+
 // Everything a product needs, as device pointers into the caller's buffer.
 struct DevH2 {
     int n_vox = 0;
@@ -65,6 +76,8 @@ struct DevH2 {
     // per-level lists for the upward / downward passes
     const int* up_list = nullptr;       // parents with rank > 0, grouped by level (deepest first)
     const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)
+
+    LeafInfo leaves;
 
     TierData tier[3];
     bool has_tier[3] = {true, false, false};

@@ -241,7 +241,9 @@ __global__ void k_init_g(double2* __restrict__ g, int m, const double* __restric
 }
 
 struct Work {
-    double2 *V, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
+    double2 *V, *Zs, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
+    float *mX, *mH1, *mH2, *mY;
+    double* mnorm;
     float2 *lo_in, *lo_out;
     double *cs, *scal, *npart;
     double2* dpart;
@@ -250,7 +252,8 @@ struct Work {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-size_t work_layout(int64_t N, int m, Work* W, char* base) {
+size_t work_layout(int64_t N, int m, Work* W, char* base, int precond = 0, int64_t nleaf = 0, int n_in = 0,
+                   int n_hidden = 0, int n_out = 0) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -261,6 +264,14 @@ size_t work_layout(int64_t N, int m, Work* W, char* base) {
     Work w{};
     w.ldv = ldv;
     w.V = (double2*)take(size_t(ldv) * (m + 1) * 16);
+    w.Zs = precond ? (double2*)take(size_t(ldv) * m * 16) : nullptr;
+    if (precond == 2) {
+        w.mX = (float*)take(size_t(nleaf) * n_in * 4);
+        w.mH1 = (float*)take(size_t(nleaf) * n_hidden * 4);
+        w.mH2 = (float*)take(size_t(nleaf) * n_hidden * 4);
+        w.mY = (float*)take(size_t(nleaf) * n_out * 4);
+        w.mnorm = (double*)take(64);
+    }
     w.w = (double2*)take(N * 16);
     w.r = (double2*)take(N * 16);
     w.z = (double2*)take(N * 16);
@@ -283,6 +294,7 @@ size_t work_layout(int64_t N, int m, Work* W, char* base) {
 
 struct Solver {
     h2_handle h;
+    int precond = 0;
     const DevH2* d;
     const LevelLaunch* lv;
     hipStream_t s;
@@ -319,24 +331,37 @@ struct Solver {
         k_reduce_partial<<<1, 128, 0, s>>>(W.dpart, nblk, nvec, out, accumulate);
     }
 
-    // GMRES(m) on Z x = rhs with x0 = 0 (x overwritten).  prec: product tier.
-    // Returns status; fills its/mv/restarts and the final true relative residual.
+    // z = P(v) for the right preconditioner
+    hipError_t apply_precond(const double2* v, double2* z) {
+        if (precond == 1) return launch_bd_apply(d->leaves, d->perm, (const double2*)h->bd_buf, v, z, s);
+        return mlp_apply_handle(h, v, z, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s);
+    }
+
+    // GMRES(m) on Z x = rhs from x0 = 0, or from the given x when use_x0 (x overwritten).
+    // prec: product tier.  Returns status; fills its/mv/restarts and the final true relative residual.
     h2_status gmres(int prec, const double2* rhs, double2* x, int m, int max_mv, double tol, int* its, int* mv,
-                    int* restarts, double* relres) {
+                    int* restarts, double* relres, bool use_x0 = false) {
         hipError_t e;
         *its = 0;
         *mv = 0;
         *restarts = 0;
-        k_fill<<<nblk, 256, 0, s>>>(x, N);
-        // r = rhs (x0 = 0)
-        e = hipMemcpyAsync(W.r, rhs, N * 16, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        if (use_x0) {
+            // r = rhs - Z x0
+            if ((e = matvec(prec, x, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+            ++*mv;
+            k_residual<<<nblk, 256, 0, s>>>(rhs, W.z, W.r, N, W.npart);
+        } else {
+            k_fill<<<nblk, 256, 0, s>>>(x, N);
+            e = hipMemcpyAsync(W.r, rhs, N * 16, hipMemcpyDeviceToDevice, s);   // r = rhs (x0 = 0)
+            if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        }
         (void)norm_into(rhs, 2);              // scal[2] = ||b||
         (void)norm_into(W.r, 3);              // scal[3] = ||r||
         if ((e = fetch(4)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         const double bnorm = host[2];
         if (!std::isfinite(bnorm)) return handle_fail(H2_ERR_NUMERIC, "right-hand side holds NaN or Inf");
-        if (bnorm == 0.0) {
+        if (bnorm == 0.0) {   // Z x = 0 has the unique solution x = 0, whatever x0 was
+            k_fill<<<nblk, 256, 0, s>>>(x, N);
             *relres = 0.0;
             return H2_OK;
         }
@@ -352,7 +377,13 @@ struct Solver {
             int jend = 0;
             for (int j = 0; j < m; ++j) {
                 double2* vj = W.V + (int64_t)j * W.ldv;
-                if ((e = matvec(prec, vj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                const double2* zj = vj;
+                if (precond) {
+                    double2* zz = W.Zs + (int64_t)j * W.ldv;
+                    if ((e = apply_precond(vj, zz)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                    zj = zz;
+                }
+                if ((e = matvec(prec, zj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
                 ++*mv;
                 ++*its;
                 multidot(j + 1, W.w, W.hcol, 0);                                           // h = V^H w
@@ -370,7 +401,7 @@ struct Solver {
                 k_scale<<<nblk, 256, 0, s>>>(W.w, W.V + (int64_t)(j + 1) * W.ldv, N, W.scal, 0);
             }
             k_backsolve<<<1, 1, 0, s>>>(W.H, m + 1, jend, W.g, W.y);
-            k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y
+            k_multiaxpy<<<nblk, 256, 0, s>>>(precond ? W.Zs : W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y (Z y)
             // true residual r = rhs - Z x (product in the same tier)
             if ((e = matvec(prec, x, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
             ++*mv;
@@ -393,7 +424,9 @@ extern "C" h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, siz
     if (!o || !bytes) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
     if (o->restart < 1 || o->restart > 127) return handle_fail(H2_ERR_INVALID_ARG, "restart must be in [1, 127]");
     const DevH2* d = handle_dev(h);
-    *bytes = work_layout(int64_t(d->n_vox) * kNcomp, o->restart, nullptr, nullptr);
+    if (o->precond == H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
+    *bytes = work_layout(int64_t(d->n_vox) * kNcomp, o->restart, nullptr, nullptr, o->precond, d->leaves.n,
+                         h->mlp_dims.n_in, h->mlp_dims.n_hidden, h->mlp_dims.n_out);
     return H2_OK;
 }
 
@@ -409,9 +442,15 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     const DevH2* d = handle_dev(h);
     if (!d->has_tier[o->precision]) return handle_fail(H2_ERR_INVALID_ARG, "precision tier was not built");
     if (o->precision == H2_BF16X3) return handle_fail(H2_ERR_INVALID_ARG, "BF16X3 product is not available in this build");
+    if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP) return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
+    if (o->precond == H2_PRECOND_BLOCKDIAG && !h->bd_ready)
+        return handle_fail(H2_ERR_INVALID_ARG, "block-diagonal preconditioner not formed (h2_precond_blockdiag)");
+    if (o->precond == H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
     const int64_t N = int64_t(d->n_vox) * kNcomp;
     const int m = o->restart;
-    const size_t need = work_layout(N, m, nullptr, nullptr);
+    const int pc = o->precond;
+    const size_t need = work_layout(N, m, nullptr, nullptr, pc, d->leaves.n, h->mlp_dims.n_in, h->mlp_dims.n_hidden,
+                                    h->mlp_dims.n_out);
     if (work_bytes < need) return handle_fail(H2_ERR_OOM, "GMRES workspace too small");
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~uintptr_t(255));
     Solver S{};
@@ -421,7 +460,8 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     S.s = reinterpret_cast<hipStream_t>(stream);
     S.N = N;
     S.nblk = int(std::min<int64_t>(kDotBlocks, (N + 255) / 256));
-    work_layout(N, m, &S.W, base);
+    work_layout(N, m, &S.W, base, pc, d->leaves.n, h->mlp_dims.n_in, h->mlp_dims.n_hidden, h->mlp_dims.n_out);
+    S.precond = pc;
     if (hipHostMalloc((void**)&S.host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
     *rep = h2_gmres_report{};
@@ -431,7 +471,7 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     if (o->precision == H2_FP64) {
         int its, mv, rs;
         double rr;
-        st = S.gmres(0, bb, xx, m, o->max_matvec, o->tol, &its, &mv, &rs, &rr);
+        st = S.gmres(0, bb, xx, m, o->max_matvec, o->tol, &its, &mv, &rs, &rr, o->use_x0 != 0);
         rep->iterations = its;
         rep->matvecs = mv;
         rep->restarts = rs;
@@ -441,16 +481,27 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
         // iterative refinement: r = b - Z x (FP64), inner GMRES with the low-precision product, x += d
         st = H2_OK;
         hipError_t e = hipSuccess;
-        k_fill<<<S.nblk, 256, 0, S.s>>>(xx, N);
+        if (!o->use_x0) k_fill<<<S.nblk, 256, 0, S.s>>>(xx, N);
         (void)S.norm_into(bb, 2);
         if ((e = S.fetch(3)) != hipSuccess) st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         const double bnorm = S.host[2];
         if (st == H2_OK && !std::isfinite(bnorm)) st = handle_fail(H2_ERR_NUMERIC, "right-hand side holds NaN or Inf");
         double rel = 0.0;
+        if (st == H2_OK && bnorm == 0.0 && o->use_x0) k_fill<<<S.nblk, 256, 0, S.s>>>(xx, N);   // x = 0 solves Z x = 0
         // rhs of the inner solve lives in W.xs (the residual), the correction in W.d
         if (st == H2_OK && bnorm > 0) {
-            e = hipMemcpyAsync(S.W.xs, bb, N * 16, hipMemcpyDeviceToDevice, S.s);
             rel = 1.0;
+            if (o->use_x0) {   // residual of the given iterate
+                if ((e = launch_matvec(*d, *S.lv, 1, 0, xx, S.W.z, 1, N, S.s)) != hipSuccess)
+                    st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                rep->matvecs += 1;
+                k_residual<<<S.nblk, 256, 0, S.s>>>(bb, S.W.z, S.W.xs, N, S.W.npart);
+                k_finish_norm<<<1, 64, 0, S.s>>>(S.W.npart, S.nblk, S.W.scal, 3);
+                if (st == H2_OK && (e = S.fetch(4)) != hipSuccess) st = handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                rel = S.host[3] / bnorm;
+            } else {
+                e = hipMemcpyAsync(S.W.xs, bb, N * 16, hipMemcpyDeviceToDevice, S.s);
+            }
             int outer = 0;
             while (st == H2_OK) {
                 if (rel <= o->tol) break;

@@ -54,6 +54,11 @@ struct Plan {
     std::vector<int> row_cl, row_ncols, row_colptr, colsrc;
     std::vector<int64_t> row_off;
     std::vector<int> up_list, down_list;
+    std::vector<int> lc_beg, lc_size;           // leaves in cluster order
+    std::vector<int64_t> lc_diag, lc_inv;
+    int64_t lc_inv_elems = 0;
+    int lc_max = 0;
+    size_t o_lbeg = 0, o_lsize = 0, o_ldiag = 0, o_linv = 0;
     LevelLaunch lv;
     int coef_rows = 0, depth = 0, max_rank = 0, min_leaf_rank = 1 << 30;
     int tiers = 1;
@@ -238,6 +243,22 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         P.near_ptr.push_back(int(P.near_off.size()));
     }
 
+    // leaves in cluster order with their diagonal near block (per-leaf preconditioners)
+    for (int c = 0; c < nc; ++c) {
+        if (d->nchild[c] != 0) continue;
+        const int n = int(d->end[c] - d->begin[c]);
+        int64_t diag = -1;
+        for (int64_t i = nfirst[c]; i < nfirst[c] + ncount[c]; ++i)
+            if (d->near_s[i] == c) diag = d->near_off[i];
+        if (diag < 0) return fail(H2_ERR_BAD_DESC, "leaf %d has no diagonal near block", c);
+        P.lc_beg.push_back(int(d->begin[c]));
+        P.lc_size.push_back(n);
+        P.lc_diag.push_back(diag);
+        P.lc_inv.push_back(P.lc_inv_elems);
+        P.lc_inv_elems += 2 * int64_t(n) * n;
+        P.lc_max = std::max(P.lc_max, n);
+    }
+
     // coupling rows: every cluster with rank > 0 (rows without blocks produce zeros)
     std::vector<int64_t> ffirst(nc, -1), fcount(nc, 0), fcols(nc, 0);
     for (int64_t i = 0; i < d->n_far; ++i) {
@@ -301,6 +322,10 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     P.o_colsrc = L.add(ints(P.colsrc.size()));
     P.o_rowoff = L.add(i64s(P.row_off.size()));
     P.o_up = L.add(ints(P.up_list.size()));
+    P.o_lbeg = L.add(ints(P.lc_beg.size()));
+    P.o_lsize = L.add(ints(P.lc_size.size()));
+    P.o_ldiag = L.add(i64s(P.lc_diag.size()));
+    P.o_linv = L.add(i64s(P.lc_inv.size()));
     P.o_down = L.add(ints(P.down_list.size()));
     const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
     for (int tier = 0; tier < 3; ++tier)
@@ -396,6 +421,10 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     errs.push_back(put(P.o_colsrc, P.colsrc.data(), P.colsrc.size() * 4));
     errs.push_back(put(P.o_rowoff, P.row_off.data(), P.row_off.size() * 8));
     errs.push_back(put(P.o_up, P.up_list.data(), P.up_list.size() * 4));
+    errs.push_back(put(P.o_lbeg, P.lc_beg.data(), P.lc_beg.size() * 4));
+    errs.push_back(put(P.o_lsize, P.lc_size.data(), P.lc_size.size() * 4));
+    errs.push_back(put(P.o_ldiag, P.lc_diag.data(), P.lc_diag.size() * 8));
+    errs.push_back(put(P.o_linv, P.lc_inv.data(), P.lc_inv.size() * 8));
     errs.push_back(put(P.o_down, P.down_list.data(), P.down_list.size() * 4));
     const double* src[4] = {d->near_blocks, d->coupling, d->basis, d->transfer};
     const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
@@ -446,6 +475,13 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.colsrc = (const int*)(base + P.o_colsrc);
     D.row_off = (const int64_t*)(base + P.o_rowoff);
     D.up_list = (const int*)(base + P.o_up);
+    D.leaves.n = int(P.lc_beg.size());
+    D.leaves.beg = (const int*)(base + P.o_lbeg);
+    D.leaves.size = (const int*)(base + P.o_lsize);
+    D.leaves.diag = (const int64_t*)(base + P.o_ldiag);
+    D.leaves.inv_off = (const int64_t*)(base + P.o_linv);
+    D.leaves.inv_elems = P.lc_inv_elems;
+    D.leaves.max_leaf = P.lc_max;
     D.down_list = (const int*)(base + P.o_down);
     for (int tier = 0; tier < 3; ++tier) {
         D.has_tier[tier] = (P.tiers >> tier) & 1;

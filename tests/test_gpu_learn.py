@@ -1,0 +1,221 @@
+"""GPU per-leaf preconditioners through the C ABI: MLP passes and Adam against the
+FP64 oracle on the same bf16 weights, leaf features, the block-diagonal inverse,
+flexible GMRES against the oracle's, and resuming a solve from a saved iterate."""
+import numpy as np
+import pytest
+
+import h2gen
+from conftest import built
+from oracle import krylov
+from oracle import matvec as om
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+_OPS = {}
+
+
+def operator(name):
+    from paper_1703_01175_amd import H2Operator
+    if name not in _OPS:
+        g, d = built(name)
+        _OPS[name] = (g, d, H2Operator(d, tiers=("fp64",)))
+    return _OPS[name]
+
+
+def _split(L, w):
+    """Flat master vector -> oracle parameter dict (row-major W1, b1, W2, b2, W3, b3)."""
+    n_in, h, n_out = L
+    out, o = {}, 0
+    for k, shape in (("W1", (h, n_in)), ("b1", (h,)), ("W2", (h, h)), ("b2", (h,)), ("W3", (n_out, h)),
+                     ("b3", (n_out,))):
+        n = int(np.prod(shape))
+        out[k] = np.asarray(w[o:o + n], np.float32).reshape(shape)
+        o += n
+    assert o == w.size
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n_pad,hidden,n", [(9, 40, 77), (27, 256, 300), (64, 256, 130)])
+def test_mlp_forward_and_gradients_vs_oracle(torch, n_pad, hidden, n):
+    from paper_1703_01175_amd import LeafMLP
+    print(f"[gpu] mlp grad n_pad={n_pad} hidden={hidden} n={n}", flush=True)
+    net = LeafMLP(n_pad, hidden, seed=5)
+    L = (7 * n_pad, hidden, 6 * n_pad)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((n, L[0])).astype(np.float32)
+    T = rng.standard_normal((n, L[2])).astype(np.float32)
+    p = omlp.rounded(_split(L, net.master()))
+    Y_ref = omlp.forward(p, X.astype(np.float64))
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert _rel(Y, Y_ref) <= 1e-5
+    loss_ref, g_ref = omlp.loss_and_grads(p, X.astype(np.float64), T.astype(np.float64))
+    g, loss = net.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    g = _split(L, g.cpu().numpy())
+    assert abs(float(loss.item()) - loss_ref) <= 1e-5 * loss_ref
+    for k in g_ref:
+        assert _rel(g[k], g_ref[k]) <= 1e-4, k
+
+
+def test_adam_step_vs_oracle(torch):
+    from paper_1703_01175_amd import LeafMLP
+    n_pad, hidden, n = 9, 40, 64
+    net = LeafMLP(n_pad, hidden, seed=6)
+    L = (7 * n_pad, hidden, 6 * n_pad)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((n, L[0])).astype(np.float32)
+    T = rng.standard_normal((n, L[2])).astype(np.float32)
+    master = _split(L, net.master())
+    lr = 1e-3
+    _, g_ref = omlp.loss_and_grads(omlp.rounded(master), X.astype(np.float64), T.astype(np.float64))
+    ref = {k: v.copy() for k, v in master.items()}
+    m = {k: np.zeros_like(v, np.float64) for k, v in master.items()}
+    v = {k: np.zeros_like(v, np.float64) for k, v in master.items()}
+    omlp.adam_step(ref, m, v, g_ref, 1, lr)
+    net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs=1, batch=n, lr=lr)
+    new = _split(L, net.master())
+    for k in master:
+        d_dev = new[k].astype(np.float64) - master[k]
+        d_ref = ref[k].astype(np.float64) - master[k]
+        big = np.abs(g_ref[k]) > 1e-4 * np.abs(g_ref[k]).max() + 1e-30
+        # the first Adam step moves every weight by about lr * sign(g)
+        assert np.all(np.abs(d_dev - d_ref) <= 2.0001 * lr), k
+        assert np.max(np.abs(d_dev[big] - d_ref[big]), initial=0.0) <= 1e-3 * lr + 2e-7 * np.abs(master[k]).max(), k
+
+
+def test_training_reduces_loss(torch):
+    from paper_1703_01175_amd import LeafMLP
+    n_pad, hidden, n = 9, 64, 2000
+    net = LeafMLP(n_pad, hidden, seed=7)
+    L = (7 * n_pad, hidden, 6 * n_pad)
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal((n, L[0])).astype(np.float32)
+    A = rng.standard_normal((L[0], L[2])) / np.sqrt(L[0])
+    T = (X @ A).astype(np.float32)             # a learnable (linear) map
+    losses = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs=30, batch=128, lr=2e-3)
+    print("[gpu] losses", losses[0], losses[-1], flush=True)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.2 * losses[0]
+
+
+@pytest.mark.parametrize("name", ["cube12", "cube13"])
+def test_leaf_features_and_targets_vs_oracle(torch, name):
+    g, d, H = operator(name)
+    nl, mx = H.leaf_count()
+    leaves = np.nonzero(d.nchild == 0)[0]
+    assert nl == leaves.size and mx == int((d.end[leaves] - d.begin[leaves]).max())
+    n_pad = 64
+    r = h2gen.random_vector(3 * g.n_vox, 21)
+    e = h2gen.random_vector(3 * g.n_vox, 22)
+    X_ref, _, _ = omlp.leaf_features(d, r, n_pad)
+    T_ref = omlp.leaf_targets(d, e, r, n_pad)
+    X = H.features(torch.from_numpy(r).cuda(), n_pad).cpu().numpy()
+    T = H.targets(torch.from_numpy(e).cuda(), torch.from_numpy(r).cuda(), n_pad).cpu().numpy()
+    assert np.allclose(X, X_ref, rtol=1e-6, atol=1e-7)
+    assert np.allclose(T, T_ref, rtol=1e-6, atol=1e-7)
+    with pytest.raises(Exception):
+        H.features(torch.from_numpy(r).cuda(), mx - 1)
+
+
+@pytest.mark.parametrize("name", ["cube12", "cube13", "rod"])
+def test_blockdiag_apply_vs_oracle(torch, name):
+    g, d, H = operator(name)
+    H.precond_blockdiag()
+    r = h2gen.random_vector(3 * g.n_vox, 23)
+    z = H.precond_apply(torch.from_numpy(r).cuda(), "blockdiag").cpu().numpy()
+    z_ref = omlp.blockdiag_apply(d, r)
+    assert _rel(z, z_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("base", ["none", "blockdiag"])
+def test_mlp_apply_vs_oracle(torch, base):
+    from paper_1703_01175_amd import LeafMLP
+    g, d, H = operator("cube13")
+    _, mx = H.leaf_count()
+    n_pad = mx
+    net = LeafMLP(n_pad, 256, seed=8)
+    if base == "blockdiag":
+        H.precond_blockdiag()
+    H.attach_mlp(net, base=base)
+    r = h2gen.random_vector(3 * g.n_vox, 24)
+    z = H.precond_apply(torch.from_numpy(r).cuda(), "mlp").cpu().numpy()
+    L = (7 * n_pad, 256, 6 * n_pad)
+    z_ref = omlp.apply(d, omlp.rounded(_split(L, net.master())), r, n_pad, on_blockdiag=(base == "blockdiag"))
+    assert _rel(z, z_ref) <= 1e-5
+
+
+def test_fgmres_blockdiag_matches_oracle(torch):
+    g, d, H = operator("rod")
+    H.precond_blockdiag()
+    Z = om.densify(d)
+    b = h2gen.random_vector(3 * g.n_vox, 25)
+    x, rep = H.gmres(torch.from_numpy(b).cuda(), tol=1e-8, restart=20, precond="blockdiag")
+    xo, ro = krylov.gmres(lambda v: Z @ v, b, tol=1e-8, restart=20, precond=lambda v: omlp.blockdiag_apply(d, v))
+    assert rep.converged and ro.converged
+    assert abs(rep.iterations - ro.iterations) <= 1
+    x = x.cpu().numpy()
+    assert np.linalg.norm(b - Z @ x) <= 1.0001e-8 * np.linalg.norm(b)
+    assert _rel(x, xo) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fgmres_mlp_converges(torch, precision):
+    """An MLP trained on (residual, error) pairs as a correction on top of the
+    block-diagonal solve, inside flexible GMRES: the true FP64 residual decides."""
+    from paper_1703_01175_amd import H2Operator, LeafMLP
+    g, d = built("cube12")
+    H = H2Operator(d, tiers=("fp64", "fp32"))
+    _, mx = H.leaf_count()
+    net = LeafMLP(mx, 64, seed=9, zero_output=True)
+    H.precond_blockdiag()
+    Xs, Ts = [], []
+    for sd in range(6):
+        r = torch.from_numpy(h2gen.random_vector(3 * g.n_vox, 100 + sd)).cuda()
+        e, rep = H.gmres(r, tol=1e-10, restart=50)        # e = Z^-1 r
+        assert rep.converged
+        Xs.append(H.features(r, mx))
+        Ts.append(H.targets(e - H.precond_apply(r, "blockdiag"), r, mx))
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    losses = net.train(X, T, epochs=40, batch=64, lr=1e-3)
+    assert losses[-1] < losses[0]
+    H.attach_mlp(net, base="blockdiag")
+    b = h2gen.plane_wave(g, 26)[0]
+    bt = torch.from_numpy(b).cuda()
+    x, rep = H.gmres(bt, tol=1e-6, restart=30, precond="mlp", precision=precision)
+    _, rep_bd = H.gmres(bt, tol=1e-6, restart=30, precond="blockdiag", precision=precision)
+    print(f"[gpu] fgmres {precision}: mlp {rep.iterations} its, blockdiag {rep_bd.iterations} its", flush=True)
+    assert rep.converged
+    assert float(np.linalg.norm(b - om.h2_matvec(d, x.cpu().numpy())) / np.linalg.norm(b)) <= 1.0001e-6
+    H.close()
+
+
+def test_resume_from_saved_iterate(torch):
+    g, d, H = operator("cube12")
+    b = h2gen.plane_wave(g, 27)[0]
+    bt = torch.from_numpy(b).cuda()
+    x1, rep1 = H.gmres(bt, tol=1e-3, restart=10)
+    assert rep1.converged and rep1.rel_residual <= 1e-3
+    x2, rep2 = H.gmres(bt, tol=1e-9, restart=10, x0=x1)
+    x3, rep3 = H.gmres(bt, tol=1e-9, restart=10)
+    assert rep2.converged and rep3.converged
+    # the resumed solve starts from the saved residual: fewer new iterations
+    assert rep2.iterations < rep3.iterations
+    Zx2 = om.h2_matvec(d, x2.cpu().numpy())
+    assert np.linalg.norm(b - Zx2) <= 1.0001e-9 * np.linalg.norm(b)
+    assert _rel(x2.cpu().numpy(), x3.cpu().numpy()) <= 1e-7
+    # an x0 that already solves the system returns at once
+    x4, rep4 = H.gmres(bt, tol=1e-6, restart=10, x0=x3)
+    assert rep4.converged and rep4.iterations == 0
