@@ -80,6 +80,13 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="batched BF16x3 workload: 256 plane waves on the 64^3 cube plus 32 uneven cubes in one group")
     ap.add_argument("--n-small", type=int, default=32, help="uneven cubes in the batched workload")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned-preconditioner experiment on the layered slab (pairs, training, FGMRES)")
+    ap.add_argument("--slab", default="96x96x48", help="slab voxels for --learned")
+    ap.add_argument("--thickness", type=float, default=2.0, help="slab thickness in wavelengths for --learned")
+    ap.add_argument("--train-rhs", type=int, default=4, help="training right-hand sides for --learned")
+    ap.add_argument("--pairs", type=int, default=20000, help="training (leaf, iterate) pairs for --learned")
+    ap.add_argument("--epochs", type=int, default=40, help="training epochs for --learned")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -108,6 +115,8 @@ def main():
 
     if args.batched:
         return batched(args)
+    if args.learned:
+        return learned(args)
 
     edge, side, eps_r, seed, eps = WORKLOADS[args.workload]
     # host construction first, before anything touches the GPU
@@ -344,6 +353,121 @@ def batched(args):
         "host_build_s": round(build_s, 1),
     }
     print(json.dumps(out), flush=True)
+
+
+
+
+def learned(args):
+    """Learned per-leaf preconditioner on the layered slab (6 layers, eps_r U[1, 10], seed 5).
+
+    Pairs come from the solver's own FP64 histories on seeded training plane waves
+    (seeds 1000..): x* solves to 1e-9, iterates x_k are the solver's saved states at
+    residual levels 1e-1 .. 1e-4 (each resumed from the last), r_k = b - Z x_k and
+    e_k = x* - x_k.  Input: the leaf's r_k, Re chi and the 26 neighbour leaves' mean
+    r_k; target: the leaf's e_k minus its block-diagonal solve (the network corrects
+    the fallback).  A seeded choice of `pairs` (iterate, leaf) rows trains the MLP
+    (Adam, on the GPU).  Evaluation on an unseen plane wave (seed 7): GMRES(50) with
+    no preconditioner, FGMRES(50) with the block-diagonal fallback and with the MLP,
+    to 1e-6, FP64 and FP32-refinement; and the one-shot error of each map on an
+    unseen residual, ||e - P(r)|| / ||e||."""
+    import numpy as np
+    import torch
+
+    import h2gen
+    from h2gen.construct import build_h2
+    from paper_1703_01175_amd import H2Operator, LeafMLP, leaf_neighbors
+
+    shape = tuple(int(a) for a in args.slab.split("x"))
+    g = h2gen.slab(shape, thickness_wavelengths=args.thickness, n_layers=6, eps_range=(1.0, 10.0), seed=5)
+    t0 = time.time()
+    d = build_h2(g, eps=1e-3, verbose=True)
+    build_s = time.time() - t0
+    log(f"[learned] host construction {build_s:.1f}s, N = {3 * g.n_vox}")
+    H = H2Operator(d, tiers=("fp64", "fp32"))
+    N = 3 * g.n_vox
+    nl, mx = H.leaf_count()
+    H.set_halo(leaf_neighbors(d, g.shape))
+    H.precond_blockdiag()
+    sync = torch.cuda.synchronize
+
+    # ---- pairs from the solver's histories
+    t0 = time.time()
+    Xs, Ts = [], []
+    levels = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4]
+    for i in range(args.train_rhs):
+        b = torch.from_numpy(h2gen.plane_wave(g, 1000 + i)[0]).cuda()
+        xs, rep = H.gmres(b, tol=1e-9, restart=50)
+        x = None
+        for lvl in levels:
+            x, _ = H.gmres(b, tol=lvl, restart=50, x0=x)
+            r = b - H.matvec(x)
+            e = xs - x
+            Xs.append(H.features(r, mx))
+            Ts.append(H.targets(e - H.precond_apply(r, "blockdiag"), r, mx))
+        log(f"[learned] training rhs {i}: x* in {rep.iterations} its")
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    del Xs, Ts
+    rng = np.random.default_rng(5)
+    sel = torch.from_numpy(rng.choice(X.shape[0], size=min(args.pairs, X.shape[0]), replace=False)).cuda()
+    X, T = X[sel].contiguous(), T[sel].contiguous()
+    sync()
+    pairs_s = time.time() - t0
+
+    # ---- training on the GPU
+    net = LeafMLP(mx, 256, seed=5, zero_output=True, halo_slots=26)
+    t0 = time.time()
+    losses = net.train(X, T, epochs=args.epochs, batch=256, lr=1e-3, seed=5)
+    sync()
+    train_s = time.time() - t0
+    log(f"[learned] trained {args.epochs} epochs in {train_s:.1f}s, loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+    H.attach_mlp(net, base="blockdiag")
+
+    # ---- evaluation on an unseen right-hand side
+    b = torch.from_numpy(h2gen.plane_wave(g, 7)[0]).cuda()
+    bn = float(torch.linalg.vector_norm(b))
+    res = {}
+    for prec in ("fp64", "fp32"):
+        for pc in ("none", "blockdiag", "mlp"):
+            H.gmres(b, tol=1e-6, restart=50, precond=pc, precision=prec)     # warm-up
+            sync()
+            t0 = time.time()
+            x, rep = H.gmres(b, tol=1e-6, restart=50, precond=pc, precision=prec)
+            sync()
+            dt = time.time() - t0
+            true_res = float(torch.linalg.vector_norm(b - H.matvec(x))) / bn
+            res[f"{prec}_{pc}"] = {"iterations": rep.iterations, "matvecs": rep.matvecs, "solve_ms": round(dt * 1e3, 2),
+                                   "true_rel_residual_fp64": true_res, "converged": bool(rep.converged)}
+            log(f"[learned] {prec} {pc}: {rep.iterations} its, {dt * 1e3:.1f} ms, true residual {true_res:.3g}")
+    # one-shot error of each map on an unseen residual (level 1e-2)
+    xs, _ = H.gmres(b, tol=1e-9, restart=50)
+    x, _ = H.gmres(b, tol=1e-2, restart=50)
+    r = b - H.matvec(x)
+    e = xs - x
+    en = float(torch.linalg.vector_norm(e))
+    one_shot = {"identity": float(torch.linalg.vector_norm(e - r)) / en,
+                "blockdiag": float(torch.linalg.vector_norm(e - H.precond_apply(r, "blockdiag"))) / en,
+                "mlp": float(torch.linalg.vector_norm(e - H.precond_apply(r, "mlp"))) / en}
+    # cost of one application of each map
+    app_ms = {}
+    for pc in ("blockdiag", "mlp"):
+        H.precond_apply(r, pc)
+        sync()
+        t0 = time.time()
+        for _ in range(20):
+            H.precond_apply(r, pc)
+        sync()
+        app_ms[pc] = round((time.time() - t0) / 20 * 1e3, 3)
+    out = {"metric": "fgmres_time_per_rhs_learned", "value": res["fp64_mlp"]["solve_ms"], "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"slab{args.slab}", "n_unknowns": N, "thickness_wavelengths": args.thickness,
+                      "layers": 6, "eps_r": [1.0, 10.0], "leaves": nl, "max_leaf": mx, "halo_slots": 26,
+                      "hidden": 256, "train_rhs": args.train_rhs, "pairs": int(X.shape[0]), "epochs": args.epochs},
+           "solves": res, "one_shot_error": one_shot, "apply_ms": app_ms,
+           "train": {"loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+                     "train_s": round(train_s, 2), "pairs_s": round(pairs_s, 2)},
+           "host_build_s": round(build_s, 1)}
+    print(json.dumps(out), flush=True)
+    H.close()
 
 
 if __name__ == "__main__":

@@ -232,7 +232,14 @@ h2_status h2_mlp_train(const h2_mlp_dims* dims, void* params, const float* X, co
                        size_t work_bytes, void* stream);
 
 h2_status h2_leaf_count(h2_handle h, int32_t* n_leaves, int32_t* max_leaf);
-/* Features (n_leaves x 7 n_pad) of a residual r (device complex double, length N);
+/* Halo inputs: nbr (host, n_leaves x slots int32, leaves numbered in cluster order,
+ * -1 for none) lists each leaf's neighbour leaves; the features then end with
+ * 6 values per slot, the neighbour's mean [Re r_c, Im r_c] / s over its voxels
+ * (c = 0..2), and n_in = 7 n_pad + 6 slots.  The library keeps a device copy and an
+ * n_leaves x 6 buffer of means (so calls on one handle that overlap race).
+ * slots = 0 removes the halo.  Detaches any attached MLP. */
+h2_status h2_leaf_halo(h2_handle h, const int32_t* nbr, int32_t slots);
+/* Features (n_leaves x (7 n_pad + 6 halo slots)) of a residual r (device complex double, length N);
  * leaves in cluster order.  scratch: 64 bytes of device memory. */
 h2_status h2_leaf_features(h2_handle h, int32_t n_pad, const void* r, float* X, void* scratch, void* stream);
 /* Targets (n_leaves x 6 n_pad) [Re e_t, Im e_t] / s with s from ||r|| (same scaling as the features). */

@@ -80,14 +80,42 @@ def adam_step(master, m, v, g, step: int, lr: float, b1: float = 0.9, b2: float 
         master[k] = (master[k] - lr * mh / (np.sqrt(vh) + eps)).astype(np.float32)
 
 
-def leaf_features(d, r: np.ndarray, n_pad: int):
-    """Features of every leaf for a residual r (caller order, length 3 n_vox); returns (X, leaves, s)."""
+def halo_table(d, shape):
+    """Neighbour leaves on the voxel grid: for leaf q and offset o in {-1, 0, 1}^3
+    (lexicographic, origin skipped), the leaf that holds the voxel at the leaf's
+    centre voxel (lower middle) plus o times the leaf's extent; -1 off the grid."""
+    leaves = [int(t) for t in np.nonzero(np.asarray(d.nchild) == 0)[0]]
+    perm = np.asarray(d.perm)
+    leaf_of = {}
+    boxes = []
+    for q, t in enumerate(leaves):
+        pts = [np.unravel_index(int(v), shape) for v in perm[d.begin[t]:d.end[t]]]
+        for p in pts:
+            leaf_of[tuple(int(c) for c in p)] = q
+        lo = [min(p[a] for p in pts) for a in range(3)]
+        hi = [max(p[a] for p in pts) for a in range(3)]
+        boxes.append((lo, hi))
+    offsets = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]
+    table = np.full((len(leaves), len(offsets)), -1, np.int64)
+    for q, (lo, hi) in enumerate(boxes):
+        for j, o in enumerate(offsets):
+            probe = tuple(lo[a] + (hi[a] - lo[a]) // 2 + o[a] * (hi[a] - lo[a] + 1) for a in range(3))
+            if all(0 <= probe[a] < shape[a] for a in range(3)):
+                table[q, j] = leaf_of[probe]
+    return table
+
+
+def leaf_features(d, r: np.ndarray, n_pad: int, halo=None):
+    """Features of every leaf for a residual r (caller order, length 3 n_vox); returns (X, leaves, s).
+    With a neighbour table, 6 values per slot follow: the neighbour's mean [Re r_c, Im r_c] / s."""
     N = r.shape[0]
     s = float(np.linalg.norm(r)) / np.sqrt(N)
     s = s if s > 0 else 1.0
     leaves = np.nonzero(np.asarray(d.nchild) == 0)[0]
-    X = np.zeros((leaves.size, 7 * n_pad))
+    slots = 0 if halo is None else halo.shape[1]
+    X = np.zeros((leaves.size, 7 * n_pad + 6 * slots))
     R = r.reshape(-1, 3)
+    means = np.zeros((leaves.size, 6))
     for q, t in enumerate(leaves):
         vox = np.asarray(d.perm)[d.begin[t]:d.end[t]]
         n = vox.size
@@ -95,6 +123,13 @@ def leaf_features(d, r: np.ndarray, n_pad: int):
         X[q, :3 * n] = rt.real.reshape(-1)
         X[q, 3 * n_pad:3 * n_pad + 3 * n] = rt.imag.reshape(-1)
         X[q, 6 * n_pad:6 * n_pad + n] = np.asarray(d.chi)[vox].real
+        means[q, :3] = rt.real.mean(0)
+        means[q, 3:] = rt.imag.mean(0)
+    for q in range(leaves.size):
+        for j in range(slots):
+            nb = int(halo[q, j])
+            if nb >= 0:
+                X[q, 7 * n_pad + 6 * j:7 * n_pad + 6 * j + 6] = means[nb]
     return X, leaves, s
 
 
@@ -128,10 +163,10 @@ def scatter(d, Y: np.ndarray, s: float, n_pad: int, N: int) -> np.ndarray:
     return z.reshape(-1)
 
 
-def apply(d, p, r: np.ndarray, n_pad: int, on_blockdiag: bool = False) -> np.ndarray:
+def apply(d, p, r: np.ndarray, n_pad: int, on_blockdiag: bool = False, halo=None) -> np.ndarray:
     """z = MLP correction of every leaf, assembled in caller order; with on_blockdiag
     the correction is added to the block-diagonal solve of r."""
-    X, leaves, s = leaf_features(d, r, n_pad)
+    X, leaves, s = leaf_features(d, r, n_pad, halo)
     z = scatter(d, forward(p, X), s, n_pad, r.shape[0])
     return z + blockdiag_apply(d, r) if on_blockdiag else z
 

@@ -7,4 +7,4 @@ library is missing.
 """
 
 from ._lib import H2Error, load  # noqa: F401
-from .api import H2Operator, H2Group, GmresResult, LeafMLP  # noqa: F401
+from .api import H2Operator, H2Group, GmresResult, LeafMLP, leaf_neighbors  # noqa: F401

@@ -122,6 +122,7 @@ def load() -> C.CDLL:
         ("h2_mlp_train", [pd, vp, vp, vp, C.c_int64, vp, C.c_int32, C.c_int32, C.c_float, vp, vp, sz, vp]),
         ("h2_leaf_count", [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         ("h2_leaf_features", [vp, C.c_int32, vp, vp, vp, vp]),
+        ("h2_leaf_halo", [vp, vp, C.c_int32]),
         ("h2_leaf_targets", [vp, C.c_int32, vp, vp, vp, vp, vp]),
         ("h2_precond_blockdiag_bytes", [vp, C.POINTER(sz)]),
         ("h2_precond_blockdiag", [vp, vp, sz, vp]),

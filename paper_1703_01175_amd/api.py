@@ -99,11 +99,22 @@ class H2Operator:
         _lib.check(self.lib.h2_leaf_count(self.handle, C.byref(n), C.byref(m)))
         return int(n.value), int(m.value)
 
+    def set_halo(self, nbr):
+        """Neighbour-leaf table (n_leaves, slots) int32, -1 for none; None removes the halo."""
+        import numpy as np
+        if nbr is None:
+            _lib.check(self.lib.h2_leaf_halo(self.handle, None, 0))
+            self.halo_slots = 0
+            return
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        _lib.check(self.lib.h2_leaf_halo(self.handle, C.c_void_p(nbr.ctypes.data), int(nbr.shape[1])))
+        self.halo_slots = int(nbr.shape[1])
+
     def features(self, r, n_pad: int, stream=None):
-        """(n_leaves, 7 n_pad) float32 features of a residual r (complex128, length N)."""
+        """(n_leaves, 7 n_pad + 6 halo slots) float32 features of a residual r (complex128, length N)."""
         import torch
         nl, _ = self.leaf_count()
-        X = torch.empty((nl, 7 * n_pad), dtype=torch.float32, device=self.device)
+        X = torch.empty((nl, 7 * n_pad + 6 * getattr(self, "halo_slots", 0)), dtype=torch.float32, device=self.device)
         scratch = torch.empty(64, dtype=torch.uint8, device=self.device)
         _lib.check(self.lib.h2_leaf_features(self.handle, n_pad, C.c_void_p(r.data_ptr()), C.c_void_p(X.data_ptr()),
                                              C.c_void_p(scratch.data_ptr()), _stream_ptr(stream)))
@@ -239,26 +250,50 @@ class H2Group:
             pass
 
 
+def leaf_neighbors(d, shape):
+    """Neighbour table of the leaves (cluster order) on a voxel grid of `shape`:
+    slot o in {-1, 0, 1}^3 minus the origin (lexicographic) holds the leaf containing
+    the voxel one leaf extent away from the leaf's centre voxel, or -1 off the grid."""
+    import numpy as np
+    nchild = np.asarray(d.nchild)
+    leaves = np.nonzero(nchild == 0)[0]
+    perm = np.asarray(d.perm)
+    begin, end = np.asarray(d.begin)[leaves], np.asarray(d.end)[leaves]
+    xyz = np.stack(np.unravel_index(perm, shape), 1)               # tree order
+    order = np.argsort(begin)                                      # leaves tile [0, n_vox) in tree order
+    lo, hi = np.empty((leaves.size, 3), np.int64), np.empty((leaves.size, 3), np.int64)
+    lo[order] = np.minimum.reduceat(xyz, begin[order], axis=0)
+    hi[order] = np.maximum.reduceat(xyz, begin[order], axis=0)
+    ext = hi - lo + 1
+    owner = np.empty(perm.size, np.int64)                           # leaf number of every voxel
+    owner[perm[np.concatenate([np.arange(begin[q], end[q]) for q in order])]] = np.repeat(order, (end - begin)[order])
+    offs = np.array([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)])
+    probe = lo[:, None, :] + offs[None, :, :] * ext[:, None, :] + ((ext - 1) // 2)[:, None, :]
+    inside = np.all((probe >= 0) & (probe < np.asarray(shape)), axis=2)
+    flat = np.ravel_multi_index(tuple(np.clip(probe, 0, np.asarray(shape) - 1).transpose(2, 0, 1)), shape)
+    return np.where(inside, owner[flat], -1).astype(np.int32)
+
+
 class LeafMLP:
     """The per-leaf MLP: parameters and workspaces in device memory, passes in the library."""
 
     def __init__(self, n_pad: int, hidden: int = 256, seed: int = 0, batch: int = 512, device: str = "cuda",
-                 zero_output: bool = False):
+                 zero_output: bool = False, halo_slots: int = 0):
         """zero_output: start with a zero last layer (output 0), for a correction on top of another map."""
         import numpy as np
         import torch
         self.lib = _lib.load()
         self.n_pad = int(n_pad)
-        self.dims = _lib.MlpDims(7 * n_pad, hidden, 6 * n_pad)
+        self.dims = _lib.MlpDims(7 * n_pad + 6 * halo_slots, hidden, 6 * n_pad)
         self.device = torch.device(device)
         pb, wb = C.c_size_t(0), C.c_size_t(0)
         _lib.check(self.lib.h2_mlp_sizes(C.byref(self.dims), batch, C.byref(pb), C.byref(wb)))
         self.params = torch.empty(int(pb.value), dtype=torch.uint8, device=self.device)
         self.batch = batch
-        self.nmaster = hidden * 7 * n_pad + hidden + hidden * hidden + hidden + 6 * n_pad * hidden + 6 * n_pad
+        n_in, h, n_out = self.dims.n_in, hidden, 6 * n_pad
+        self.nmaster = h * n_in + h + h * h + h + n_out * h + n_out
         # He-normal initial weights drawn here (seeded) and handed to the library
         rng = np.random.default_rng(seed)
-        n_in, h, n_out = 7 * n_pad, hidden, 6 * n_pad
         parts = [rng.standard_normal(h * n_in) * np.sqrt(2.0 / n_in), np.zeros(h),
                  rng.standard_normal(h * h) * np.sqrt(2.0 / h), np.zeros(h),
                  rng.standard_normal(n_out * h) * np.sqrt(1.0 / h) * (0.0 if zero_output else 1.0), np.zeros(n_out)]

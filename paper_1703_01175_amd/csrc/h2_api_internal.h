@@ -114,7 +114,12 @@ struct h2_handle_s {
     h2_mlp_dims mlp_dims{0, 0, 0};
     int mlp_npad = 0;
     int mlp_base = 0;                   // H2_PRECOND_NONE, or BLOCKDIAG: z = BD(r) + MLP correction
+    int* halo_nbr = nullptr;            // n_leaves x halo_slots neighbour leaves (-1: none), library memory
+    float* halo_means = nullptr;        // n_leaves x 6 scaled leaf means of the current input, library memory
+    int halo_slots = 0;
     ~h2_handle_s() {
+        if (halo_nbr) (void)hipFree(halo_nbr);
+        if (halo_means) (void)hipFree(halo_means);
         if (self_group) h2::group_destroy(self_group);
         delete batch;
         delete prof;

@@ -162,9 +162,11 @@ __global__ void k_zero_f(float* __restrict__ p, int64_t n) {
 
 // ---------------------------------------------------------------- leaf features and corrections
 // s = ||r|| / sqrt(N) from a device norm; features of every leaf (cluster order)
+// (halo block: the scaled means of the neighbour leaves listed in nbr, 6 values per slot)
 __global__ void k_leaf_features(int nleaf, int n_pad, const int* __restrict__ lbeg, const int* __restrict__ lsize,
                                 const int* __restrict__ perm, const double2* __restrict__ chi,
                                 const double2* __restrict__ r, const double* __restrict__ norm, double sqrtN,
+                                const int* __restrict__ nbr, int slots, const float* __restrict__ means,
                                 float* __restrict__ X) {
     const int t = blockIdx.x;
     if (t >= nleaf) return;
@@ -172,7 +174,12 @@ __global__ void k_leaf_features(int nleaf, int n_pad, const int* __restrict__ lb
     double s = norm[0] / sqrtN;
     if (!(s > 0.0)) s = 1.0;
     const double inv = 1.0 / s;
-    float* x = X + (int64_t)t * 7 * n_pad;
+    const int n_in = 7 * n_pad + 6 * slots;
+    float* x = X + (int64_t)t * n_in;
+    for (int e = 7 * n_pad + threadIdx.x; e < n_in; e += blockDim.x) {
+        const int q = e - 7 * n_pad, nb = nbr[(int64_t)t * slots + q / 6];
+        x[e] = nb >= 0 ? means[(int64_t)nb * 6 + q % 6] : 0.f;
+    }
     for (int e = threadIdx.x; e < 7 * n_pad; e += blockDim.x) {
         float v = 0.f;
         if (e < 3 * n_pad) {
@@ -186,6 +193,37 @@ __global__ void k_leaf_features(int nleaf, int n_pad, const int* __restrict__ lb
             if (i < n) v = float(chi[perm[b + i]].x);
         }
         x[e] = v;
+    }
+}
+
+// Scaled leaf means [Re m_c, Im m_c] (c = 0..2) of r / s, one 64-lane group per leaf (leaves hold <= 64 voxels).
+__global__ __launch_bounds__(64) void k_leaf_means(int nleaf, const int* __restrict__ lbeg, const int* __restrict__ lsize,
+                                                   const int* __restrict__ perm, const double2* __restrict__ r,
+                                                   const double* __restrict__ norm, double sqrtN, float* __restrict__ means) {
+    __shared__ double red[6][64];
+    const int t = blockIdx.x;
+    const int n = lsize[t], b = lbeg[t];
+    const int i = threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        const int64_t p = (int64_t)perm[b + i] * 3;
+        for (int c = 0; c < 3; ++c) {
+            const double2 a = r[p + c];
+            v[c] = a.x;
+            v[3 + c] = a.y;
+        }
+    }
+    for (int q = 0; q < 6; ++q) red[q][i] = v[q];
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (i < w)
+            for (int q = 0; q < 6; ++q) red[q][i] += red[q][i + w];
+        __syncthreads();
+    }
+    if (i < 6) {
+        double s = norm[0] / sqrtN;
+        if (!(s > 0.0)) s = 1.0;
+        means[(int64_t)t * 6 + i] = float(red[i][0] / (double(n) * s));
     }
 }
 
@@ -582,10 +620,12 @@ namespace h2 {
 
 // device launch helpers used by h2vie_api.cpp and the solver
 hipError_t launch_leaf_features(const LeafInfo& li, int n_pad, const int* perm, const double2* chi, const double2* r,
-                                double* norm_scratch, int64_t N, float* X, hipStream_t s) {
+                                double* norm_scratch, int64_t N, const int* nbr, int slots, float* means, float* X,
+                                hipStream_t s) {
     k_norm_full<<<1, 256, 0, s>>>(r, N, norm_scratch);
+    if (slots > 0) k_leaf_means<<<li.n, 64, 0, s>>>(li.n, li.beg, li.size, perm, r, norm_scratch, std::sqrt(double(N)), means);
     k_leaf_features<<<li.n, 256, 0, s>>>(li.n, n_pad, li.beg, li.size, perm, chi, r, norm_scratch,
-                                         std::sqrt(double(N)), X);
+                                         std::sqrt(double(N)), nbr, slots, means, X);
     return hipGetLastError();
 }
 
@@ -619,7 +659,8 @@ hipError_t mlp_apply_handle(h2_handle h, const double2* r, double2* z, float* X,
     const DevH2& D = h->dev;
     const MlpLayout L = mlp_layout(h->mlp_dims.n_in, h->mlp_dims.n_hidden, h->mlp_dims.n_out);
     const int64_t N = int64_t(D.n_vox) * kNcomp;
-    hipError_t e = launch_leaf_features(D.leaves, h->mlp_npad, D.perm, D.chi, r, norm, N, X, s);
+    hipError_t e = launch_leaf_features(D.leaves, h->mlp_npad, D.perm, D.chi, r, norm, N, h->halo_nbr, h->halo_slots,
+                                        h->halo_means, X, s);
     if (e != hipSuccess) return e;
     mlp_forward_dev(L, h->mlp_params, X, H1, H2, Y, D.leaves.n, s);
     const bool on_bd = h->mlp_base == H2_PRECOND_BLOCKDIAG;
@@ -651,7 +692,8 @@ h2_status h2_leaf_features(h2_handle h, int32_t n_pad, const void* r, float* X, 
     if (n_pad < h->dev.leaves.max_leaf || n_pad > 4096) return handle_fail(H2_ERR_INVALID_ARG, "n_pad below the largest leaf");
     const DevH2& D = h->dev;
     hipError_t e = launch_leaf_features(D.leaves, n_pad, D.perm, D.chi, (const double2*)r, (double*)scratch,
-                                        int64_t(D.n_vox) * kNcomp, X, reinterpret_cast<hipStream_t>(stream));
+                                        int64_t(D.n_vox) * kNcomp, h->halo_nbr, h->halo_slots, h->halo_means, X,
+                                        reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
     return H2_OK;
 }
@@ -710,12 +752,35 @@ h2_status h2_precond_mlp(h2_handle h, const h2_mlp_dims* dims, int32_t n_pad, vo
         return handle_fail(H2_ERR_INVALID_ARG, "the MLP's base must be PRECOND_NONE or PRECOND_BLOCKDIAG");
     if (base == H2_PRECOND_BLOCKDIAG && !h->bd_ready)
         return handle_fail(H2_ERR_INVALID_ARG, "block-diagonal base not formed (h2_precond_blockdiag first)");
-    if (n_pad < h->dev.leaves.max_leaf || dims->n_in != 7 * n_pad || dims->n_out != 6 * n_pad)
-        return handle_fail(H2_ERR_INVALID_ARG, "MLP sizes must be n_in = 7 n_pad, n_out = 6 n_pad, n_pad >= largest leaf");
+    if (n_pad < h->dev.leaves.max_leaf || dims->n_in != 7 * n_pad + 6 * h->halo_slots || dims->n_out != 6 * n_pad)
+        return handle_fail(H2_ERR_INVALID_ARG,
+                           "MLP sizes must be n_in = 7 n_pad + 6 halo slots, n_out = 6 n_pad, n_pad >= largest leaf");
     h->mlp_params = params;
     h->mlp_dims = *dims;
     h->mlp_npad = n_pad;
     h->mlp_base = base;
+    return H2_OK;
+}
+
+h2_status h2_leaf_halo(h2_handle h, const int32_t* nbr, int32_t slots) {
+    if (!handle_live(h)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (slots < 0 || slots > 124 || (slots > 0 && !nbr)) return handle_fail(H2_ERR_INVALID_ARG, "slots must be in [0, 124]");
+    const int nl = h->dev.leaves.n;
+    for (int64_t i = 0; i < int64_t(nl) * slots; ++i)
+        if (nbr[i] < -1 || nbr[i] >= nl) return handle_fail(H2_ERR_INVALID_ARG, "neighbour index out of range");
+    if (h->halo_nbr) (void)hipFree(h->halo_nbr);
+    if (h->halo_means) (void)hipFree(h->halo_means);
+    h->halo_nbr = nullptr;
+    h->halo_means = nullptr;
+    h->halo_slots = 0;
+    h->mlp_params = nullptr;          // an attached MLP no longer matches the feature size
+    if (slots == 0) return H2_OK;
+    if (hipMalloc((void**)&h->halo_nbr, size_t(nl) * slots * 4) != hipSuccess ||
+        hipMalloc((void**)&h->halo_means, size_t(nl) * 6 * 4) != hipSuccess)
+        return handle_fail(H2_ERR_OOM, "halo tables: device allocation failed");
+    if (hipMemcpy(h->halo_nbr, nbr, size_t(nl) * slots * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return handle_fail(H2_ERR_DEVICE, "halo table upload failed");
+    h->halo_slots = slots;
     return H2_OK;
 }
 

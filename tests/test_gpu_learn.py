@@ -130,6 +130,26 @@ def test_leaf_features_and_targets_vs_oracle(torch, name):
         H.features(torch.from_numpy(r).cuda(), mx - 1)
 
 
+@pytest.mark.parametrize("name", ["cube12", "box9"])
+def test_halo_features_vs_oracle(torch, name):
+    from paper_1703_01175_amd import H2Operator, leaf_neighbors
+    g, d = built(name)
+    H = H2Operator(d, tiers=("fp64",))
+    tab = leaf_neighbors(d, g.shape)
+    H.set_halo(tab)
+    _, mx = H.leaf_count()
+    r = h2gen.random_vector(3 * g.n_vox, 31)
+    X_ref, _, _ = omlp.leaf_features(d, r, mx, omlp.halo_table(d, g.shape))
+    X = H.features(torch.from_numpy(r).cuda(), mx).cpu().numpy()
+    assert X.shape == X_ref.shape == (tab.shape[0], 7 * mx + 6 * 26)
+    assert np.allclose(X, X_ref, rtol=1e-6, atol=1e-7)
+    bad = tab.copy()
+    bad[0, 0] = tab.shape[0]
+    with pytest.raises(Exception):
+        H.set_halo(bad)
+    H.close()
+
+
 @pytest.mark.parametrize("name", ["cube12", "cube13", "rod"])
 def test_blockdiag_apply_vs_oracle(torch, name):
     g, d, H = operator(name)
@@ -140,21 +160,27 @@ def test_blockdiag_apply_vs_oracle(torch, name):
     assert _rel(z, z_ref) <= 1e-12
 
 
-@pytest.mark.parametrize("base", ["none", "blockdiag"])
-def test_mlp_apply_vs_oracle(torch, base):
-    from paper_1703_01175_amd import LeafMLP
-    g, d, H = operator("cube13")
+@pytest.mark.parametrize("base,halo", [("none", False), ("blockdiag", False), ("blockdiag", True)])
+def test_mlp_apply_vs_oracle(torch, base, halo):
+    from paper_1703_01175_amd import H2Operator, LeafMLP, leaf_neighbors
+    g, d = built("cube13")
+    H = H2Operator(d, tiers=("fp64",))
     _, mx = H.leaf_count()
     n_pad = mx
-    net = LeafMLP(n_pad, 256, seed=8)
+    slots = 26 if halo else 0
+    if halo:
+        H.set_halo(leaf_neighbors(d, g.shape))
+    net = LeafMLP(n_pad, 256, seed=8, halo_slots=slots)
     if base == "blockdiag":
         H.precond_blockdiag()
     H.attach_mlp(net, base=base)
     r = h2gen.random_vector(3 * g.n_vox, 24)
     z = H.precond_apply(torch.from_numpy(r).cuda(), "mlp").cpu().numpy()
-    L = (7 * n_pad, 256, 6 * n_pad)
-    z_ref = omlp.apply(d, omlp.rounded(_split(L, net.master())), r, n_pad, on_blockdiag=(base == "blockdiag"))
+    L = (7 * n_pad + 6 * slots, 256, 6 * n_pad)
+    z_ref = omlp.apply(d, omlp.rounded(_split(L, net.master())), r, n_pad, on_blockdiag=(base == "blockdiag"),
+                       halo=omlp.halo_table(d, g.shape) if halo else None)
     assert _rel(z, z_ref) <= 1e-5
+    H.close()
 
 
 def test_fgmres_blockdiag_matches_oracle(torch):

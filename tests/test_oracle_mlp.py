@@ -125,3 +125,50 @@ def test_features_and_apply_layout():
     vox = d.perm[d.begin[leaves[q]]:d.end[leaves[q]]]
     assert np.array_equal(X[q, 6 * 64:6 * 64 + vox.size], g.chi[vox].real)
     assert not X[q, 6 * 64 + vox.size:].any()
+
+
+def test_halo_table_on_a_uniform_leaf_grid():
+    """On the 12^3 cube every leaf is a 3^3 block on a 4^3 grid of leaves: the table is
+    the 26-neighbourhood of that grid, -1 exactly where it leaves the grid."""
+    from conftest import built
+    g, d = built("cube12")
+    tab = mlp.halo_table(d, g.shape)
+    leaves = np.nonzero(d.nchild == 0)[0]
+    cell = []
+    for t in leaves:
+        xyz = np.stack(np.unravel_index(d.perm[d.begin[t]:d.end[t]], g.shape), 1)
+        assert (xyz.max(0) - xyz.min(0) + 1 == 3).all() and d.end[t] - d.begin[t] == 27
+        cell.append(tuple(xyz.min(0) // 3))
+    where = {c: q for q, c in enumerate(cell)}
+    offs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]
+    for q, c in enumerate(cell):
+        for j, o in enumerate(offs):
+            nb = tuple(c[a] + o[a] for a in range(3))
+            assert tab[q, j] == where.get(nb, -1)
+    # symmetric: o and -o are reverse slots
+    for q in range(len(cell)):
+        for j in range(26):
+            if tab[q, j] >= 0:
+                assert tab[tab[q, j], 25 - j] == q
+
+
+def test_halo_features_are_neighbour_means():
+    from conftest import built
+    import h2gen
+    g, d = built("box9")                       # uneven leaves
+    tab = mlp.halo_table(d, g.shape)
+    r = h2gen.random_vector(3 * g.n_vox, 9)
+    X0, leaves, s = mlp.leaf_features(d, r, 64)
+    X, _, _ = mlp.leaf_features(d, r, 64, tab)
+    assert np.array_equal(X[:, :7 * 64], X0)
+    R = r.reshape(-1, 3) / s
+    for q in range(0, leaves.size, 5):
+        for j in range(26):
+            nb = tab[q, j]
+            blk = X[q, 7 * 64 + 6 * j:7 * 64 + 6 * j + 6]
+            if nb < 0:
+                assert not blk.any()
+            else:
+                vox = d.perm[d.begin[leaves[nb]]:d.end[leaves[nb]]]
+                m = R[vox].sum(0) / vox.size
+                assert np.allclose(blk, np.concatenate([m.real, m.imag]), rtol=0, atol=1e-14)
