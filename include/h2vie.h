@@ -184,6 +184,22 @@ h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes)
 h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o,
                          h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
 
+/* Solve Z x_c = b_c for n_rhs right-hand sides at once (the paper's many
+ * right-hand sides, Sec. IV.D): every column runs its own restarted GMRES (FP64
+ * Arnoldi, CGS2, Givens, own basis and Hessenberg matrix) in lockstep with the
+ * others, so that each product is one multi-column product.  precision FP64:
+ * plain restarted GMRES; FP32 / BF16X3: iterative refinement with the outer
+ * residual b_c - Z x_c in FP64 and the inner solves (to inner_tol relative to
+ * the outer residual) on the lower-precision product; BF16X3 needs the tier and
+ * n_rhs <= max_rhs.  precond as for h2_gmres_solve (flexible GMRES per column).
+ * b, x: device complex double, column c at b + c * ld, ld >= N; x is the start
+ * when use_x0, else overwritten.  reps: host array of n_rhs reports.
+ * Synchronises the stream.  Returns OK when every column reached tol,
+ * NOT_CONVERGED otherwise (x holds the last iterates), or an error. */
+h2_status h2_gmres_batch_workspace(h2_handle h, int64_t n_rhs, int64_t ld, const h2_gmres_opts* o, size_t* bytes);
+h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void* b, void* x, int64_t ld, const h2_gmres_opts* o,
+                               h2_gmres_report* reps, void* work, size_t work_bytes, void* stream);
+
 typedef struct {
     int64_t n_vox, n_clusters, n_leaves, n_far, n_near, depth;
     int64_t near_elems, coupling_elems, basis_elems, transfer_elems;  /* complex counts */

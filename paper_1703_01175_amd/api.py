@@ -93,6 +93,35 @@ class H2Operator:
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
                               rep.rel_residual)
 
+    def gmres_batch(self, B, X=None, tol: float = 1e-6, restart: int = 30, max_matvec: int = 10000,
+                    precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 30, precond: str = "none",
+                    X0=None, stream=None):
+        """Solve Z x_c = b_c for the rows of B (n_rhs, N) complex128 in lockstep; every
+        product is one multi-column product.  Returns X and one GmresResult per row."""
+        import torch
+        if B.dtype != torch.complex128 or not B.is_cuda or B.dim() != 2 or B.shape[1] != self.N:
+            raise ValueError("B must be a complex128 CUDA tensor of shape (n_rhs, N)")
+        B = B.contiguous()
+        n = int(B.shape[0])
+        if X is None:
+            X = torch.empty_like(B)
+        use_x0 = 0
+        if X0 is not None:
+            X.copy_(X0)
+            use_x0 = 1
+        opts = _lib.GmresOpts(restart=restart, max_matvec=max_matvec, tol=tol, precision=_lib.PRECISION[precision],
+                              inner_tol=inner_tol, max_outer=max_outer, precond=_lib.PRECOND[precond], use_x0=use_x0)
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.h2_gmres_batch_workspace(self.handle, n, self.N, C.byref(opts), C.byref(nbytes)))
+        work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        reps = (_lib.GmresReport * n)()
+        st = self.lib.h2_gmres_solve_batch(self.handle, n, C.c_void_p(B.data_ptr()), C.c_void_p(X.data_ptr()), self.N,
+                                           C.byref(opts), reps, C.c_void_p(work.data_ptr()), nbytes,
+                                           _stream_ptr(stream))
+        _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
+        return X, [GmresResult(bool(r.converged), r.iterations, r.matvecs, r.restarts, r.outer, r.rel_residual)
+                   for r in reps]
+
     # ------------------------------------------------------------------ per-leaf preconditioners
     def leaf_count(self):
         n, m = C.c_int32(0), C.c_int32(0)

@@ -1,0 +1,109 @@
+"""Batched GMRES through the C ABI: every column must behave as its own solve.
+Judged by the oracle's FP64 residual and against the single-right-hand-side solver."""
+import numpy as np
+import pytest
+
+import h2gen
+from conftest import built
+from oracle import matvec as om
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+_OPS = {}
+
+
+def operator(name):
+    from paper_1703_01175_amd import H2Operator
+    if name not in _OPS:
+        g, d = built(name)
+        _OPS[name] = (g, d, H2Operator(d, tiers=("fp64", "fp32", "bf16x3"), max_rhs=8))
+    return _OPS[name]
+
+
+def _rhs(g, n, seed):
+    waves = h2gen.plane_wave(g, seed, count=n)
+    return np.ascontiguousarray(waves)
+
+
+def _true_res(d, x, b):
+    return float(np.linalg.norm(b - om.h2_matvec(d, x)) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", ["cube12", "box9"])
+def test_batch_fp64_matches_single_solves(torch, name):
+    print(f"[gpu] batch fp64 {name}", flush=True)
+    g, d, H = operator(name)
+    B = _rhs(g, 5, 41)
+    X, reps = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-8, restart=12)
+    X = X.cpu().numpy()
+    for c in range(B.shape[0]):
+        x1, r1 = H.gmres(torch.from_numpy(B[c]).cuda(), tol=1e-8, restart=12)
+        assert reps[c].converged and r1.converged
+        assert abs(reps[c].iterations - r1.iterations) <= 1
+        assert _true_res(d, X[c], B[c]) <= 1.0001e-8
+        assert np.linalg.norm(X[c] - x1.cpu().numpy()) <= 1e-6 * np.linalg.norm(X[c])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_batch_refinement_reaches_fp64_tolerance(torch, precision):
+    print(f"[gpu] batch {precision}", flush=True)
+    g, d, H = operator("cube12")
+    B = _rhs(g, 8, 42)
+    X, reps = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-8, restart=20, precision=precision, inner_tol=1e-3)
+    X = X.cpu().numpy()
+    for c in range(B.shape[0]):
+        assert reps[c].converged and reps[c].outer >= 2
+        assert _true_res(d, X[c], B[c]) <= 1.0001e-8
+
+
+def test_batch_uneven_columns_and_zero_rhs(torch):
+    """Columns of very different difficulty (and an all-zero one) in one batch."""
+    g, d, H = operator("cube12")
+    B = _rhs(g, 4, 43)
+    B[1] *= 1e-9                               # tiny but nonzero
+    B[2] = 0.0
+    B[3] = h2gen.random_vector(3 * g.n_vox, 44)
+    X, reps = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-7, restart=8, precision="bf16x3")
+    X = X.cpu().numpy()
+    assert all(r.converged for r in reps)
+    assert not X[2].any() and reps[2].iterations == 0
+    for c in (0, 1, 3):
+        assert _true_res(d, X[c], B[c]) <= 1.0001e-7
+
+
+def test_batch_blockdiag_matches_single(torch):
+    g, d, H = operator("box9")
+    H.precond_blockdiag()
+    B = _rhs(g, 3, 45)
+    X, reps = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-8, restart=10, precond="blockdiag")
+    X = X.cpu().numpy()
+    for c in range(B.shape[0]):
+        _, r1 = H.gmres(torch.from_numpy(B[c]).cuda(), tol=1e-8, restart=10, precond="blockdiag")
+        assert reps[c].converged and abs(reps[c].iterations - r1.iterations) <= 1
+        assert _true_res(d, X[c], B[c]) <= 1.0001e-8
+
+
+def test_batch_resume_and_limits(torch):
+    g, d, H = operator("cube12")
+    B = torch.from_numpy(_rhs(g, 3, 46)).cuda()
+    X1, r1 = H.gmres_batch(B, tol=1e-3, restart=10)
+    X2, r2 = H.gmres_batch(B, tol=1e-9, restart=10, X0=X1)
+    X3, r3 = H.gmres_batch(B, tol=1e-9, restart=10)
+    for c in range(3):
+        assert r2[c].converged and r2[c].iterations < r3[c].iterations
+        assert _true_res(d, X2[c].cpu().numpy(), B[c].cpu().numpy()) <= 1.0001e-9
+    # budget exhausted: NOT_CONVERGED reported per column, no exception
+    _, r4 = H.gmres_batch(B, tol=1e-12, restart=5, max_matvec=4)
+    assert not any(r.converged for r in r4)
+    with pytest.raises(Exception):
+        H.gmres_batch(torch.cat([B, B, B, B]), precision="bf16x3")      # 12 > max_rhs
