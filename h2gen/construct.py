@@ -24,6 +24,7 @@ from __future__ import annotations
 import mmap
 import multiprocessing as mp
 import os
+import sys
 import time
 
 import numpy as np
@@ -303,7 +304,7 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
     if verbose:
         print(f"[h2gen] {geom.name}: {ncl} clusters, {part.n_far} far, {part.n_near} near, "
               f"{nproc} workers, keep B: {keep_b} (~{est_b/1e9:.1f} GB of {keep_b_bytes/1e9:.0f} GB budget)  "
-              f"{time.time()-t0:.1f}s", flush=True)
+              f"{time.time()-t0:.1f}s", file=sys.stderr, flush=True)
 
     st = dict(tree=tree, ker=ker, partners=partners, eps=eps, eps_aca=eps_aca, keep_b=keep_b)
     _STATE.clear()
@@ -319,7 +320,7 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
             A[c] = a
             K[c] = kk
         if verbose:
-            print(f"[h2gen] stage I {time.time()-t0:.1f}s", flush=True)
+            print(f"[h2gen] stage I {time.time()-t0:.1f}s", file=sys.stderr, flush=True)
 
         # ---- Stage II: terms covering each cluster (itself and ancestors with blocks)
         terms = [None] * ncl
@@ -386,7 +387,7 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
         if verbose:
             print(f"[h2gen] stage II bases {time.time()-t0:.1f}s; ranks " +
                   ", ".join(f"L{l}:{rank[tree.level == l].min()}-{rank[tree.level == l].max()}"
-                            for l in range(tree.depth + 1)), flush=True)
+                            for l in range(tree.depth + 1)), file=sys.stderr, flush=True)
 
         # ---- couplings S_ts = (V_t^H A_t)(V_s^H B_t|_s)^T on the workers holding B_t
         far_t, far_s = part.far_t, part.far_s
@@ -403,7 +404,7 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
                 coupling[o:o + S.size] = S.reshape(-1, order="F")
                 i += 1
         if verbose:
-            print(f"[h2gen] couplings {time.time()-t0:.1f}s ({coupling.nbytes/1e9:.2f} GB)", flush=True)
+            print(f"[h2gen] couplings {time.time()-t0:.1f}s ({coupling.nbytes/1e9:.2f} GB)", file=sys.stderr, flush=True)
     finally:
         pool.close()
 
@@ -445,7 +446,7 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
         near = np.zeros(0, np.complex128)
     _STATE.clear()
     if verbose:
-        print(f"[h2gen] near {time.time()-t0:.1f}s ({near.nbytes/1e9:.2f} GB)", flush=True)
+        print(f"[h2gen] near {time.time()-t0:.1f}s ({near.nbytes/1e9:.2f} GB)", file=sys.stderr, flush=True)
 
     meta = dict(name=geom.name, shape=list(geom.shape), h=geom.h, leaf_size=leaf_size, eta=eta, eps=eps,
                 eps_aca=eps_aca, build_seconds=time.time() - t0, geom_meta=geom.meta)

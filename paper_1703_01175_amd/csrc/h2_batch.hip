@@ -155,22 +155,33 @@ __device__ __forceinline__ bf16x8 zero8() {
     return v.b;
 }
 
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+    V8 v;
+    v.u = *reinterpret_cast<const uint4*>(p);
+    return v.b;
+}
+
 // One group per task (owner, first column); wave w owns real row tiles w and w + 4
-// of the owner (2 mp real rows) and all NC / 16 column tiles of the task.
+// of the owner (2 mp real rows) and all NC / 16 column tiles of the task.  The B
+// operand of each term (the source's rows of the task's columns, re and im, hi and
+// lo) is staged once in LDS and read from there by all four waves; each wave reads
+// its own rows of A straight from memory (A is used once per task).
 template <int NC>
 __global__ __launch_bounds__(256) void k_bgemm(const BOwner* __restrict__ owners, const BTerm* __restrict__ terms,
                                                const int2* __restrict__ tasks, const int* __restrict__ owner_cols) {
     constexpr int NCT = NC / 16;
+    constexpr int BST = 2 * 64 + 8;   // LDS column stride (bf16): 2 kp <= 128 real k, padded against bank conflicts
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NC * BST];   // [hi, lo][column][re k | im k]
     const int2 task = tasks[blockIdx.x];
     const BOwner O = owners[task.x];
     const int ncols = owner_cols[task.x];
     const int col0 = task.y;
+    const int nc_here = min(NC, ncols - col0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
     const int mp = O.mp;
     const int nrt = (2 * mp) / 16;
-    const bool v0 = w < nrt, v1 = (w + 4) < nrt;
-    if (!v0) return;   // no row tile for this wave (the wave never reaches a barrier)
+    const bool v0 = w < nrt, v1 = (w + 4) < nrt;   // waves without a row tile still stage B
     f32x4 acc[2][NCT];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -187,6 +198,19 @@ __global__ __launch_bounds__(256) void k_bgemm(const BOwner* __restrict__ owners
     for (int t = O.t0; t < O.t0 + O.nt; ++t) {
         const BTerm T = terms[t];
         const int kp = T.kp;
+        const int kq = kp >> 3;                       // 16-byte chunks per plane column
+        __syncthreads();                              // the previous term's B is no longer read
+        for (int e = threadIdx.x; e < NC * 4 * kq; e += 256) {
+            const int c = e / (4 * kq);
+            const int rem = e - c * 4 * kq;
+            const int plane = rem / kq, kc = rem - plane * kq;   // plane: re_hi, re_lo, im_hi, im_lo
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (c < nc_here)
+                v = *reinterpret_cast<const uint4*>(T.b + plane * T.bps + (int64_t)(col0 + c) * T.bld + kc * 8);
+            *reinterpret_cast<uint4*>(&Bs[plane & 1][c * BST + (plane >> 1) * kp + kc * 8]) = v;
+        }
+        __syncthreads();
+        if (!v0) continue;
         const int64_t pl = (int64_t)mp * kp;
         const int nks = (2 * kp) / 32;
         for (int ks = 0; ks < nks; ++ks) {
@@ -208,18 +232,10 @@ __global__ __launch_bounds__(256) void k_bgemm(const BOwner* __restrict__ owners
                     alo[r] = zero8();
                 }
             }
-            const uint16_t* pb = T.b + (kh ? 2 * T.bps : 0) + kk;
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
-                const int col = col0 + c * 16 + (l & 15);
-                bf16x8 bhi, blo;
-                if (col < ncols) {
-                    bhi = ld8(pb + (int64_t)col * T.bld);
-                    blo = ld8(pb + T.bps + (int64_t)col * T.bld);
-                } else {
-                    bhi = zero8();
-                    blo = zero8();
-                }
+                const uint16_t* pb = &Bs[0][(c * 16 + (l & 15)) * BST + kreal];
+                const bf16x8 bhi = lds8(pb), blo = lds8(pb + NC * BST);
                 acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[0], bhi, acc[0][c], 0, 0, 0);
                 acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[0], blo, acc[0][c], 0, 0, 0);
                 acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[0], bhi, acc[0][c], 0, 0, 0);
@@ -231,6 +247,7 @@ __global__ __launch_bounds__(256) void k_bgemm(const BOwner* __restrict__ owners
             }
         }
     }
+    if (!v0) return;
     // lane holds C[4 (l / 16) + q][l % 16] of each tile: 4 consecutive rows of one column
 #pragma unroll
     for (int r = 0; r < 2; ++r) {

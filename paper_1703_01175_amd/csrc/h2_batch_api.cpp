@@ -48,7 +48,9 @@ h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B) {
         if (r >= (int64_t(1) << 31)) return H2_ERR_BAD_DESC;
 
     int64_t arena = 0;
+    bool too_big = false;   // the block GEMM stages at most 64 complex k and holds at most 64 rows per block
     auto add_job = [&](int which, int64_t src, int m, int k, int src_rows, int transpose) -> int64_t {
+        too_big = too_big || m > 64 || k > 64;
         PackJob J{};
         J.src = src;
         J.dst = arena;
@@ -174,6 +176,7 @@ h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B) {
             B.near.owners.push_back(o);
         }
     }
+    if (too_big) return H2_ERR_BAD_DESC;
     B.arena_elems = arena;
     return H2_OK;
 }
