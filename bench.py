@@ -86,7 +86,9 @@ def main():
                     help="learned-preconditioner experiment on the layered slab (pairs, training, FGMRES)")
     ap.add_argument("--slab", default="96x96x48", help="slab voxels for --learned")
     ap.add_argument("--thickness", type=float, default=2.0, help="slab thickness in wavelengths for --learned")
-    ap.add_argument("--train-rhs", type=int, default=4, help="training right-hand sides for --learned")
+    ap.add_argument("--train-rhs", type=int, default=2, help="training right-hand sides for --learned")
+    ap.add_argument("--eval-rhs", type=int, default=8, help="evaluation right-hand sides (batched leg) for --learned")
+    ap.add_argument("--max-matvec", type=int, default=6000, help="product cap of each evaluation solve for --learned")
     ap.add_argument("--pairs", type=int, default=20000, help="training (leaf, iterate) pairs for --learned")
     ap.add_argument("--epochs", type=int, default=40, help="training epochs for --learned")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -365,15 +367,19 @@ def learned(args):
     """Learned per-leaf preconditioner on the layered slab (6 layers, eps_r U[1, 10], seed 5).
 
     Pairs come from the solver's own FP64 histories on seeded training plane waves
-    (seeds 1000..): x* solves to 1e-9, iterates x_k are the solver's saved states at
-    residual levels 1e-1 .. 1e-4 (each resumed from the last), r_k = b - Z x_k and
-    e_k = x* - x_k.  Input: the leaf's r_k, Re chi and the 26 neighbour leaves' mean
-    r_k; target: the leaf's e_k minus its block-diagonal solve (the network corrects
-    the fallback).  A seeded choice of `pairs` (iterate, leaf) rows trains the MLP
-    (Adam, on the GPU).  Evaluation on an unseen plane wave (seed 7): GMRES(50) with
-    no preconditioner, FGMRES(50) with the block-diagonal fallback and with the MLP,
-    to 1e-6, FP64 and FP32-refinement; and the one-shot error of each map on an
-    unseen residual, ||e - P(r)|| / ||e||."""
+    (seeds 1000..): x* solves to 1e-7 (a tenth of the target), iterates x_k are the
+    solver's saved states at residual levels 1e-1 .. 1e-4 (each resumed from the
+    last), r_k = b - Z x_k and e_k = x* - x_k.  Input: the leaf's r_k, Re chi and the
+    26 neighbour leaves' mean r_k; target: the leaf's e_k minus its block-diagonal
+    solve (the network corrects the fallback).  A seeded choice of `pairs`
+    (iterate, leaf) rows trains the MLP (Adam, on the GPU).  Evaluation on unseen
+    plane waves (seeds 7..), to 1e-6: GMRES(50) with no preconditioner, FGMRES(50)
+    with the block-diagonal fallback, the learned restart correction (x + P(r) at
+    each cycle start when it lowers the residual, cycles on the block-diagonal map),
+    and FGMRES(50) with the MLP map on every Arnoldi vector; one right-hand side in
+    FP64, and a batch on the BF16x3 product with FP64 refinement; the one-shot
+    error of each map on an unseen residual, ||e - P(r)|| / ||e||.  Every solve is
+    capped at --max-matvec products and prints as each segment ends."""
     import numpy as np
     import torch
 
@@ -387,13 +393,33 @@ def learned(args):
     d = build_h2(g, eps=1e-3, verbose=True)
     build_s = time.time() - t0
     log(f"[learned] host construction {build_s:.1f}s, N = {3 * g.n_vox}")
-    n_eval = 8
+    n_eval = args.eval_rhs
+    cap = args.max_matvec
     H = H2Operator(d, tiers=("fp64", "fp32", "bf16x3"), max_rhs=n_eval)
     N = 3 * g.n_vox
     nl, mx = H.leaf_count()
     H.set_halo(leaf_neighbors(d, g.shape))
     H.precond_blockdiag()
     sync = torch.cuda.synchronize
+    seg = 1000
+
+    def segmented(solve, tag):
+        """Long solves run in segments of at most `seg` products, each resuming from the
+        saved iterate (a restart at the segment boundary), and report as each ends."""
+        x, its, mv, t_run = None, 0, 0, 0.0
+        while True:
+            sync()
+            t0 = time.time()
+            x, rep = solve(x, min(seg, cap - mv))
+            sync()
+            t_run += time.time() - t0
+            reps = rep if isinstance(rep, list) else [rep]
+            its += max(r.iterations for r in reps)
+            mv += max(r.matvecs for r in reps)
+            done = all(r.converged for r in reps)
+            log(f"[learned]   {tag}: {its} its, worst residual {max(r.rel_residual for r in reps):.3g}, {t_run:.1f}s")
+            if done or mv >= cap:
+                return x, its, mv, t_run, done
 
     # ---- pairs from the solver's histories
     t0 = time.time()
@@ -401,15 +427,16 @@ def learned(args):
     levels = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4]
     for i in range(args.train_rhs):
         b = torch.from_numpy(h2gen.plane_wave(g, 1000 + i)[0]).cuda()
-        xs, rep = H.gmres(b, tol=1e-9, restart=50)
+        xs, _, _, _, _ = segmented(lambda x0, m: H.gmres(b, tol=1e-7, restart=50, max_matvec=m, x0=x0),
+                                   f"training rhs {i} x*")
         x = None
         for lvl in levels:
-            x, _ = H.gmres(b, tol=lvl, restart=50, x0=x)
+            x, rk = H.gmres(b, tol=lvl, restart=50, x0=x, max_matvec=cap)
             r = b - H.matvec(x)
             e = xs - x
             Xs.append(H.features(r, mx))
             Ts.append(H.targets(e - H.precond_apply(r, "blockdiag"), r, mx))
-        log(f"[learned] training rhs {i}: x* in {rep.iterations} its")
+            log(f"[learned]   iterate at {rk.rel_residual:.2g}")
     X, T = torch.cat(Xs), torch.cat(Ts)
     del Xs, Ts
     rng = np.random.default_rng(5)
@@ -427,54 +454,43 @@ def learned(args):
     log(f"[learned] trained {args.epochs} epochs in {train_s:.1f}s, loss {losses[0]:.4g} -> {losses[-1]:.4g}")
     H.attach_mlp(net, base="blockdiag")
 
-    # ---- evaluation on an unseen right-hand side
-    b = torch.from_numpy(h2gen.plane_wave(g, 7)[0]).cuda()
+    # ---- one right-hand side, FP64
+    Bev = torch.from_numpy(h2gen.plane_wave(g, 7, count=n_eval)).cuda()
+    b = Bev[0].contiguous()
     bn = float(torch.linalg.vector_norm(b))
     res = {}
-    for prec in ("fp64", "fp32"):
-        for pc in ("none", "blockdiag", "mlp"):
-            H.gmres(b, tol=1e-6, restart=50, precond=pc, precision=prec)     # warm-up
-            sync()
-            t0 = time.time()
-            x, rep = H.gmres(b, tol=1e-6, restart=50, precond=pc, precision=prec)
-            sync()
-            dt = time.time() - t0
-            true_res = float(torch.linalg.vector_norm(b - H.matvec(x))) / bn
-            res[f"{prec}_{pc}"] = {"iterations": rep.iterations, "matvecs": rep.matvecs, "solve_ms": round(dt * 1e3, 2),
-                                   "true_rel_residual_fp64": true_res, "converged": bool(rep.converged)}
-            log(f"[learned] {prec} {pc}: {rep.iterations} its, {dt * 1e3:.1f} ms, true residual {true_res:.3g}")
-    # mixed precision + batched + preconditioned: unseen plane waves (seeds 7..) solved together
-    Bev = torch.from_numpy(h2gen.plane_wave(g, 7, count=n_eval)).cuda()
-    single = []
-    sync()
-    t0 = time.time()
-    for c in range(n_eval):
-        single.append(H.gmres(Bev[c], tol=1e-6, restart=50)[1].iterations)
-    sync()
-    res["fp64_single_plain"] = {"rhs": n_eval, "ms_per_rhs": round((time.time() - t0) / n_eval * 1e3, 2),
-                                "iterations": single}
-    for pc in ("none", "blockdiag", "mlp"):
-        H.gmres_batch(Bev, tol=1e-6, restart=30, precision="bf16x3", precond=pc)    # warm-up
-        sync()
-        t0 = time.time()
-        Xb, reps = H.gmres_batch(Bev, tol=1e-6, restart=30, precision="bf16x3", precond=pc)
-        sync()
-        dt = time.time() - t0
+    H.gmres(b, tol=1e-6, restart=50, max_matvec=60)     # warm-up of every path
+    x_ref = None
+    for pc in ("none", "blockdiag", "mlp_restart", "mlp"):
+        x, its, mv, dt, ok = segmented(
+            lambda x0, m, pc=pc: H.gmres(b, tol=1e-6, restart=50, precond=pc, max_matvec=m, x0=x0), f"fp64 {pc}")
+        true_res = float(torch.linalg.vector_norm(b - H.matvec(x))) / bn
+        res[f"fp64_{pc}"] = {"iterations": its, "matvecs": mv, "solve_ms": round(dt * 1e3, 1),
+                             "true_rel_residual_fp64": true_res, "converged": ok}
+        log(f"[learned] fp64 {pc}: {its} its, {dt * 1e3:.0f} ms, true residual {true_res:.3g}")
+        if pc == "none":
+            x_ref = x.clone()
+    # ---- mixed precision + batched + preconditioned, n_eval right-hand sides
+    for pc in ("none", "blockdiag", "mlp_restart"):
+        Xb, its, mv, dt, ok = segmented(
+            lambda x0, m, pc=pc: H.gmres_batch(Bev, tol=1e-6, restart=50, precision="bf16x3", precond=pc,
+                                               max_matvec=m, X0=x0), f"bf16x3 batch {pc}")
         tr = max(float(torch.linalg.vector_norm(Bev[c] - H.matvec(Xb[c].contiguous())) /
                        torch.linalg.vector_norm(Bev[c])) for c in range(n_eval))
-        res[f"bf16x3_batch_{pc}"] = {"rhs": n_eval, "ms_per_rhs": round(dt / n_eval * 1e3, 2),
-                                     "iterations_mean": float(np.mean([r.iterations for r in reps])),
-                                     "converged": all(r.converged for r in reps), "max_true_rel_residual_fp64": tr}
-        log(f"[learned] bf16x3 batch {pc}: {dt / n_eval * 1e3:.1f} ms per rhs, true residual {tr:.3g}")
-    # one-shot error of each map on an unseen residual (level 1e-2)
-    xs, _ = H.gmres(b, tol=1e-9, restart=50)
-    x, _ = H.gmres(b, tol=1e-2, restart=50)
+        res[f"bf16x3_batch_{pc}"] = {"rhs": n_eval, "ms_per_rhs": round(dt / n_eval * 1e3, 1),
+                                     "lockstep_iterations": its, "converged": ok, "max_true_rel_residual_fp64": tr}
+        log(f"[learned] bf16x3 batch {pc}: {dt / n_eval * 1e3:.0f} ms per rhs, true residual {tr:.3g}")
+    # ---- one-shot error of each map on an unseen residual (level 1e-2); x* is the
+    # 1e-6 solution above, far closer to the solution than the 1e-2 iterate
+    xs = x_ref
+    x, _ = H.gmres(b, tol=1e-2, restart=50, max_matvec=cap)
     r = b - H.matvec(x)
     e = xs - x
     en = float(torch.linalg.vector_norm(e))
     one_shot = {"identity": float(torch.linalg.vector_norm(e - r)) / en,
                 "blockdiag": float(torch.linalg.vector_norm(e - H.precond_apply(r, "blockdiag"))) / en,
                 "mlp": float(torch.linalg.vector_norm(e - H.precond_apply(r, "mlp"))) / en}
+    log(f"[learned] one-shot error: {one_shot}")
     # cost of one application of each map
     app_ms = {}
     for pc in ("blockdiag", "mlp"):
@@ -485,11 +501,12 @@ def learned(args):
             H.precond_apply(r, pc)
         sync()
         app_ms[pc] = round((time.time() - t0) / 20 * 1e3, 3)
-    out = {"metric": "fgmres_time_per_rhs_learned", "value": res["fp64_mlp"]["solve_ms"], "unit": "ms",
-           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+    out = {"metric": "gmres_time_per_rhs_learned", "value": res["bf16x3_batch_mlp_restart"]["ms_per_rhs"], "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "bf16x3+f64", "data": "synthetic",
            "config": {"workload": f"slab{args.slab}", "n_unknowns": N, "thickness_wavelengths": args.thickness,
                       "layers": 6, "eps_r": [1.0, 10.0], "leaves": nl, "max_leaf": mx, "halo_slots": 26,
-                      "hidden": 256, "train_rhs": args.train_rhs, "pairs": int(X.shape[0]), "epochs": args.epochs},
+                      "hidden": 256, "train_rhs": args.train_rhs, "pairs": int(X.shape[0]), "epochs": args.epochs,
+                      "eval_rhs": n_eval, "max_matvec": cap},
            "solves": res, "one_shot_error": one_shot, "apply_ms": app_ms,
            "train": {"loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
                      "train_s": round(train_s, 2), "pairs_s": round(pairs_s, 2)},

@@ -143,7 +143,18 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
 h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* y, int64_t n_rhs,
                     int64_t ld, void* stream);
 
-typedef enum { H2_PRECOND_NONE = 0, H2_PRECOND_BLOCKDIAG = 1, H2_PRECOND_MLP = 2 } h2_precond;
+/* NONE: plain GMRES.  BLOCKDIAG, MLP: flexible GMRES with z_j = P(v_j) on every
+ * Arnoldi vector.  MLP_RESTART: at the start of every cycle, x + P(r) with the
+ * attached MLP map replaces x when it lowers ||b - Z x|| (one extra product per
+ * cycle); the cycles themselves run with the MLP's base map (none or block
+ * diagonal) as right preconditioner.  The network sees true residuals only, the
+ * inputs it was trained on. */
+typedef enum {
+    H2_PRECOND_NONE = 0,
+    H2_PRECOND_BLOCKDIAG = 1,
+    H2_PRECOND_MLP = 2,
+    H2_PRECOND_MLP_RESTART = 3
+} h2_precond;
 
 typedef struct {
     int32_t restart;        /* Krylov dimension m per cycle (1..128); 50 */
@@ -163,6 +174,8 @@ typedef struct {
     int32_t restarts;       /* GMRES cycles */
     int32_t outer;          /* refinement steps (0 for FP64) */
     double rel_residual;    /* true ||b - Z x|| / ||b||, FP64 product */
+    int32_t corrections;    /* accepted learned restart corrections (PRECOND_MLP_RESTART) */
+    int32_t pad;
 } h2_gmres_report;
 
 /* Workspace bytes for h2_gmres_solve with opts o (device memory, caller owned). */
@@ -178,7 +191,8 @@ h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes)
  * x += d.  With a preconditioner P the method is flexible GMRES with right
  * preconditioning: z_j = P(v_j) is stored, w = Z z_j, and x += sum y_j z_j, so P may
  * change between steps (the MLP is nonlinear).  PRECOND_BLOCKDIAG needs
- * h2_precond_blockdiag, PRECOND_MLP needs h2_precond_mlp, both first.
+ * h2_precond_blockdiag, PRECOND_MLP and PRECOND_MLP_RESTART need h2_precond_mlp,
+ * both first.
  * b, x: device complex double, length N.  Synchronises the stream.
  * Returns OK, NOT_CONVERGED (x holds the last iterate) or an error. */
 h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o,

@@ -30,6 +30,7 @@ class SolveReport:
     restarts: int
     rel_residual: float        # true ||b - A x|| / ||b|| at exit
     history: list = field(default_factory=list)   # Givens estimates per step
+    corrections: int = 0       # accepted restart corrections
 
 
 def givens(a: complex, b: complex):
@@ -46,8 +47,9 @@ def givens(a: complex, b: complex):
 
 
 def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec: int = 10000,
-          x0: np.ndarray | None = None, precond=None) -> tuple:
-    """Solve A x = b.  apply(v) -> A v; precond(v) -> z (right preconditioner, may be nonlinear)."""
+          x0: np.ndarray | None = None, precond=None, correct=None) -> tuple:
+    """Solve A x = b.  apply(v) -> A v; precond(v) -> z (right preconditioner, may be nonlinear).
+    correct(r) -> c: at every cycle start x + c replaces x when it lowers ||b - A x|| (one product)."""
     b = np.asarray(b, np.complex128)
     n = b.shape[0]
     bnorm = float(np.linalg.norm(b))
@@ -64,11 +66,23 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
         r = b - apply(x)
         mv += 1
     m = restart
+    corrections = 0
     while True:
         beta = float(np.linalg.norm(r))
         rel = beta / bnorm
         if rel <= tol or mv >= max_matvec:
-            return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist)
+            return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections)
+        if correct is not None:
+            xt = x + correct(r)
+            rt = b - apply(xt)
+            mv += 1
+            if float(np.linalg.norm(rt)) < beta:
+                x, r = xt, rt
+                corrections += 1
+                beta = float(np.linalg.norm(r))
+                rel = beta / bnorm
+                if rel <= tol or mv >= max_matvec:
+                    return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections)
         V = np.zeros((m + 1, n), np.complex128)
         Zs = np.zeros((m, n), np.complex128) if precond is not None else None
         H = np.zeros((m + 1, m), np.complex128)

@@ -24,6 +24,7 @@ class GmresResult:
     restarts: int
     outer: int
     rel_residual: float
+    corrections: int = 0
 
 
 class H2Operator:
@@ -91,7 +92,7 @@ class H2Operator:
                                      C.byref(rep), C.c_void_p(work.data_ptr()), nbytes, _stream_ptr(stream))
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
-                              rep.rel_residual)
+                              rep.rel_residual, rep.corrections)
 
     def gmres_batch(self, B, X=None, tol: float = 1e-6, restart: int = 30, max_matvec: int = 10000,
                     precision: str = "fp64", inner_tol: float = 1e-3, max_outer: int = 30, precond: str = "none",
@@ -119,8 +120,8 @@ class H2Operator:
                                            C.byref(opts), reps, C.c_void_p(work.data_ptr()), nbytes,
                                            _stream_ptr(stream))
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
-        return X, [GmresResult(bool(r.converged), r.iterations, r.matvecs, r.restarts, r.outer, r.rel_residual)
-                   for r in reps]
+        return X, [GmresResult(bool(r.converged), r.iterations, r.matvecs, r.restarts, r.outer, r.rel_residual,
+                               r.corrections) for r in reps]
 
     # ------------------------------------------------------------------ per-leaf preconditioners
     def leaf_count(self):

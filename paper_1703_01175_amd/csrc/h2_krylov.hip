@@ -175,6 +175,12 @@ __global__ void k_add(double2* __restrict__ x, const double2* __restrict__ d, in
     }
 }
 
+// out = a + b
+__global__ void k_sum(const double2* __restrict__ a, const double2* __restrict__ b, double2* __restrict__ out, int64_t N) {
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
+        out[n] = make_double2(a[n].x + b[n].x, a[n].y + b[n].y);
+}
+
 // Givens update of Hessenberg column j (single thread; j < 128).
 // H is (m+1) x m column major; hcol holds h_0..h_j, scal[0] = ||w|| = h_{j+1}.
 // scal[1] = |g_{j+1}| (residual estimate, unnormalised).
@@ -201,7 +207,7 @@ __global__ void k_init_g(double2* __restrict__ g, int m, const double* __restric
 }
 
 struct Work {
-    double2 *V, *Zs, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
+    double2 *V, *Zs, *xt, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
     float *mX, *mH1, *mH2, *mY;
     double* mnorm;
     float2 *lo_in, *lo_out;
@@ -225,7 +231,8 @@ size_t work_layout(int64_t N, int m, Work* W, char* base, int precond = 0, int64
     w.ldv = ldv;
     w.V = (double2*)take(size_t(ldv) * (m + 1) * 16);
     w.Zs = precond ? (double2*)take(size_t(ldv) * m * 16) : nullptr;
-    if (precond == 2) {
+    w.xt = precond == 3 ? (double2*)take(N * 16) : nullptr;
+    if (precond >= 2) {
         w.mX = (float*)take(size_t(nleaf) * n_in * 4);
         w.mH1 = (float*)take(size_t(nleaf) * n_hidden * 4);
         w.mH2 = (float*)take(size_t(nleaf) * n_hidden * 4);
@@ -291,11 +298,40 @@ struct Solver {
         k_reduce_partial<<<1, 128, 0, s>>>(W.dpart, nblk, nvec, out, accumulate);
     }
 
+    // Arnoldi's right preconditioner: 0 none, 1 block diagonal, 2 MLP.  With the
+    // restart correction (precond 3) the cycles use the MLP's base map.
+    int inner_pc() const { return precond == 3 ? (h->mlp_base == H2_PRECOND_BLOCKDIAG ? 1 : 0) : precond; }
+
     // z = P(v) for the right preconditioner
     hipError_t apply_precond(const double2* v, double2* z) {
-        if (precond == 1) return launch_bd_apply(d->leaves, d->perm, (const double2*)h->bd_buf, v, z, s);
+        if (inner_pc() == 1) return launch_bd_apply(d->leaves, d->perm, (const double2*)h->bd_buf, v, z, s);
         return mlp_apply_handle(h, v, z, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s);
     }
+
+    // Learned correction at a cycle start: x_try = x + P(r) with the attached MLP map;
+    // kept (x, r, beta and scal[3] replaced) only when ||rhs - Z x_try|| < beta.
+    h2_status restart_correction(int prec, const double2* rhs, double2* x, double* beta, int* mv) {
+        hipError_t e;
+        if ((e = mlp_apply_handle(h, W.r, W.w, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s)) != hipSuccess)
+            return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        k_sum<<<nblk, 256, 0, s>>>(x, W.w, W.xt, N);
+        if ((e = matvec(prec, W.xt, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        ++*mv;
+        k_residual<<<nblk, 256, 0, s>>>(rhs, W.z, W.w, N, W.npart);
+        k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 4);
+        if ((e = fetch(5)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        const double bt = host[4];
+        if (std::isfinite(bt) && bt < *beta) {
+            if ((e = hipMemcpyAsync(x, W.xt, N * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(W.r, W.w, N * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(W.scal + 3, W.scal + 4, 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+                return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+            *beta = bt;
+            ++corrections;
+        }
+        return H2_OK;
+    }
+    int corrections = 0;
 
     // GMRES(m) on Z x = rhs from x0 = 0, or from the given x when use_x0 (x overwritten).
     // prec: product tier.  Returns status; fills its/mv/restarts and the final true relative residual.
@@ -326,11 +362,19 @@ struct Solver {
             return H2_OK;
         }
         double beta = host[3];
+        const int ipc = inner_pc();
         while (true) {
             *relres = beta / bnorm;
             if (!std::isfinite(beta)) return handle_fail(H2_ERR_NUMERIC, "residual is NaN or Inf");
             if (*relres <= tol) return H2_OK;
             if (*mv >= max_mv) return H2_NOT_CONVERGED;
+            if (precond == 3) {
+                h2_status st = restart_correction(prec, rhs, x, &beta, mv);
+                if (st != H2_OK) return st;
+                *relres = beta / bnorm;
+                if (*relres <= tol) return H2_OK;
+                if (*mv >= max_mv) return H2_NOT_CONVERGED;
+            }
             // v_0 = r / beta
             k_scale<<<nblk, 256, 0, s>>>(W.r, W.V, N, W.scal, 3);
             k_init_g<<<1, 256, 0, s>>>(W.g, m, W.scal, 3);
@@ -338,7 +382,7 @@ struct Solver {
             for (int j = 0; j < m; ++j) {
                 double2* vj = W.V + (int64_t)j * W.ldv;
                 const double2* zj = vj;
-                if (precond) {
+                if (ipc) {
                     double2* zz = W.Zs + (int64_t)j * W.ldv;
                     if ((e = apply_precond(vj, zz)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
                     zj = zz;
@@ -361,7 +405,7 @@ struct Solver {
                 k_scale<<<nblk, 256, 0, s>>>(W.w, W.V + (int64_t)(j + 1) * W.ldv, N, W.scal, 0);
             }
             k_backsolve<<<1, 1, 0, s>>>(W.H, m + 1, jend, W.g, W.y);
-            k_multiaxpy<<<nblk, 256, 0, s>>>(precond ? W.Zs : W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y (Z y)
+            k_multiaxpy<<<nblk, 256, 0, s>>>(ipc ? W.Zs : W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y (Z y)
             // true residual r = rhs - Z x (product in the same tier)
             if ((e = matvec(prec, x, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
             ++*mv;
@@ -384,7 +428,7 @@ extern "C" h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, siz
     if (!o || !bytes) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
     if (o->restart < 1 || o->restart > 127) return handle_fail(H2_ERR_INVALID_ARG, "restart must be in [1, 127]");
     const DevH2* d = handle_dev(h);
-    if (o->precond == H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
+    if (o->precond >= H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
     *bytes = work_layout(int64_t(d->n_vox) * kNcomp, o->restart, nullptr, nullptr, o->precond, d->leaves.n,
                          h->mlp_dims.n_in, h->mlp_dims.n_hidden, h->mlp_dims.n_out);
     return H2_OK;
@@ -402,10 +446,11 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     const DevH2* d = handle_dev(h);
     if (!d->has_tier[o->precision]) return handle_fail(H2_ERR_INVALID_ARG, "precision tier was not built");
     if (o->precision == H2_BF16X3) return handle_fail(H2_ERR_INVALID_ARG, "BF16X3 product is not available in this build");
-    if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP) return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
+    if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP_RESTART)
+        return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
     if (o->precond == H2_PRECOND_BLOCKDIAG && !h->bd_ready)
         return handle_fail(H2_ERR_INVALID_ARG, "block-diagonal preconditioner not formed (h2_precond_blockdiag)");
-    if (o->precond == H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
+    if (o->precond >= H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
     const int64_t N = int64_t(d->n_vox) * kNcomp;
     const int m = o->restart;
     const int pc = o->precond;
@@ -492,6 +537,7 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
         rep->rel_residual = rel;
         rep->converged = (st == H2_OK);
     }
+    rep->corrections = S.corrections;
     if (hipStreamSynchronize(S.s) != hipSuccess && st >= 0) st = handle_fail(H2_ERR_DEVICE, "solve synchronisation failed");
     (void)hipHostFree(S.host);
     return st;

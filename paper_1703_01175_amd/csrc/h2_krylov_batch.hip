@@ -215,6 +215,23 @@ __global__ void kb_reduce_add(double2* __restrict__ a, const double2* __restrict
     a[(int64_t)c * kHs + i].y += b[(int64_t)c * kHs + i].y;
 }
 
+// out_c = a_c + b_c
+__global__ void kb_sum(const double2* __restrict__ a, const double2* __restrict__ b, double2* __restrict__ out,
+                       int64_t ld, int64_t N) {
+    const int c = blockIdx.z;
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
+        out[c * ld + n] = make_double2(a[c * ld + n].x + b[c * ld + n].x, a[c * ld + n].y + b[c * ld + n].y);
+}
+
+// dst_c = src_c where take[c]
+__global__ void kb_select(double2* __restrict__ dst, const double2* __restrict__ src, int64_t ld, int64_t N,
+                          const int* __restrict__ take) {
+    const int c = blockIdx.z;
+    if (!take[c]) return;
+    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
+        dst[c * ld + n] = src[c * ld + n];
+}
+
 __global__ void kb_givens(double2* __restrict__ H, int64_t hs, int ldh, int j, const double2* __restrict__ hcol,
                           double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
                           double* __restrict__ scal) {
@@ -241,11 +258,11 @@ __global__ void kb_init_g(double2* __restrict__ g, int m, const double* __restri
 
 struct BWork {
     double2 *V, *Zs;                 // bases [j][c][ld]
-    double2 *W, *Rin, *R, *D, *Zx;   // columns [c][ld]
+    double2 *W, *Rin, *R, *D, *Zx, *Dt;   // columns [c][ld]
     float2 *lo_in, *lo_out;
     double2 *hcol, *H, *sn, *g, *y, *dpart;
     double *cs, *scal, *npart;
-    int *jend, *live;
+    int *jend, *live, *acc;
     float *mX, *mH1, *mH2, *mY;
     double* mnorm;
 };
@@ -264,7 +281,8 @@ size_t bwork_layout(int64_t ld, int ncol, int m, int nblk, BWork* W, char* base,
     BWork w{};
     w.V = (double2*)take(col * (m + 1) * 16);
     w.Zs = precond ? (double2*)take(col * m * 16) : nullptr;
-    if (precond == 2) {
+    w.Dt = precond == 3 ? (double2*)take(col * 16) : nullptr;
+    if (precond >= 2) {
         w.mX = (float*)take(size_t(nleaf) * n_in * 4);
         w.mH1 = (float*)take(size_t(nleaf) * n_hidden * 4);
         w.mH2 = (float*)take(size_t(nleaf) * n_hidden * 4);
@@ -289,6 +307,7 @@ size_t bwork_layout(int64_t ld, int ncol, int m, int nblk, BWork* W, char* base,
     w.dpart = (double2*)take(size_t(ncol) * nblk * 128 * 16);
     w.jend = (int*)take(size_t(ncol) * 4);
     w.live = (int*)take(size_t(ncol) * 4);
+    w.acc = (int*)take(size_t(ncol) * 4);
     if (W) *W = w;
     return off + 256;
 }
@@ -334,10 +353,14 @@ struct BSolver {
         return H2_OK;
     }
 
+    // Arnoldi's right preconditioner: 0 none, 1 block diagonal, 2 MLP; the restart
+    // correction (3) runs its cycles with the MLP's base map.
+    int inner_pc() const { return precond == 3 ? (h->mlp_base == H2_PRECOND_BLOCKDIAG ? 1 : 0) : precond; }
+
     h2_status precondition(const double2* v, double2* z) {   // z_c = P(v_c), column by column
         for (int c = 0; c < ncol; ++c) {
             hipError_t e;
-            if (precond == H2_PRECOND_BLOCKDIAG)
+            if (inner_pc() == H2_PRECOND_BLOCKDIAG)
                 e = launch_bd_apply(d->leaves, d->perm, (const double2*)h->bd_buf, v + c * ld, z + c * ld, s);
             else
                 e = mlp_apply_handle(h, v + c * ld, z + c * ld, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s);
@@ -363,6 +386,43 @@ struct BSolver {
         return e == hipSuccess ? H2_OK : handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
     }
 
+    // Learned correction at a cycle start, per open column: d_c + P(r_c) replaces d_c
+    // (and the residual r_c) when it lowers ||rhs_c - Z d_c||.
+    h2_status restart_correction(int prec, const double2* rhs, double2* dsol, std::vector<double>& res,
+                                 const std::vector<char>& open, std::vector<int>& mv, int* spent) {
+        hipError_t e;
+        for (int c = 0; c < ncol; ++c) {
+            if (open[c])
+                e = mlp_apply_handle(h, W.Rin + c * ld, W.W + c * ld, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s);
+            else
+                e = hipMemsetAsync(W.W + c * ld, 0, size_t(N) * 16, s);
+            if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        }
+        kb_sum<<<cgrid(), 256, 0, s>>>(dsol, W.W, W.Dt, ld, N);
+        h2_status st = prod(prec, W.Dt, W.Zx);
+        if (st != H2_OK) return st;
+        ++*spent;
+        kb_residual<<<cgrid(), 256, 0, s>>>(rhs, ld, W.Zx, ld, W.W, ld, N, W.npart);
+        kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 4);
+        if ((st = fetch()) != H2_OK) return st;
+        std::vector<int> take(ncol, 0);
+        for (int c = 0; c < ncol; ++c) {
+            if (!open[c]) continue;
+            ++mv[c];
+            const double rt = host[c * kSs + 4];
+            if (std::isfinite(rt) && rt < res[c]) {
+                take[c] = 1;
+                res[c] = rt;
+                ++corrections[c];
+            }
+        }
+        if ((st = upload_ints(W.acc, take)) != H2_OK) return st;
+        kb_select<<<cgrid(), 256, 0, s>>>(dsol, W.Dt, ld, N, W.acc);
+        kb_select<<<cgrid(), 256, 0, s>>>(W.Rin, W.W, ld, N, W.acc);
+        return H2_OK;
+    }
+    std::vector<int> corrections;
+
     void multidot(int nvec, const double2* w, double2* out, int accumulate) {   // basis [j][c][ld]
         dim3 grid(nblk, (nvec + kTile - 1) / kTile, ncol);
         kb_multidot<<<grid, 256, 0, s>>>(W.V, ld * ncol, ld, nvec, w, ld, N, W.dpart);
@@ -385,6 +445,7 @@ struct BSolver {
         std::vector<char> open(ncol);
         for (int c = 0; c < ncol; ++c) res[c] = host[c * kSs + 3];
         int spent = 0;
+        const int ipc = inner_pc();
         while (true) {
             bool any = false;
             for (int c = 0; c < ncol; ++c) {
@@ -392,9 +453,17 @@ struct BSolver {
                 any = any || open[c];
             }
             if (!any || spent >= max_mv) break;
+            if (precond == 3) {
+                if ((st = restart_correction(prec, rhs, dsol, res, open, mv, &spent)) != H2_OK) return st;
+                any = false;
+                for (int c = 0; c < ncol; ++c) {
+                    open[c] = open[c] && res[c] > target[c];
+                    any = any || open[c];
+                }
+                if (!any || spent >= max_mv) break;
+            }
             // v_0 = r / ||r|| (columns that are not open start from zero and stay there)
-            for (int c = 0; c < ncol; ++c)
-                if (!open[c]) host[c * kSs + 3] = 0.0;
+            for (int c = 0; c < ncol; ++c) host[c * kSs + 3] = open[c] ? res[c] : 0.0;
             if ((e = hipMemcpyAsync(W.scal, host, size_t(ncol) * kSs * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
                 return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
             kb_scale<<<cgrid(), 256, 0, s>>>(W.Rin, ld, W.V, ld, N, W.scal, 3);
@@ -405,7 +474,7 @@ struct BSolver {
             for (int j = 0; j < m; ++j) {
                 const double2* vj = W.V + (int64_t)j * blk;
                 const double2* src = vj;
-                if (precond) {
+                if (ipc) {
                     double2* zj = W.Zs + (int64_t)j * blk;
                     if ((st = precondition(vj, zj)) != H2_OK) return st;
                     src = zj;
@@ -437,7 +506,7 @@ struct BSolver {
             // d_c += basis_c y_c over the column's own jend_c vectors
             if ((st = upload_ints(W.jend, hjend)) != H2_OK) return st;
             kb_backsolve<<<ncol, 64, 0, s>>>(W.H, int64_t(m + 1) * m, m + 1, W.jend, W.g, W.y);
-            kb_multiaxpy<<<cgrid(), 256, 0, s>>>(precond ? W.Zs : W.V, blk, ld, m, W.jend, W.y, 1.0, dsol, ld, N,
+            kb_multiaxpy<<<cgrid(), 256, 0, s>>>(ipc ? W.Zs : W.V, blk, ld, m, W.jend, W.y, 1.0, dsol, ld, N,
                                                 nullptr);
             // true inner residual rhs - Z d in the same tier
             if ((st = prod(prec, dsol, W.Zx)) != H2_OK) return st;
@@ -476,10 +545,11 @@ static h2_status batch_check(h2_handle h, int64_t n_rhs, int64_t ld, const h2_gm
     }
     if (o->precision != H2_FP64 && !(o->inner_tol > 0.0 && o->inner_tol < 1.0))
         return handle_fail(H2_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
-    if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP) return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
+    if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP_RESTART)
+        return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
     if (o->precond == H2_PRECOND_BLOCKDIAG && !h->bd_ready)
         return handle_fail(H2_ERR_INVALID_ARG, "block-diagonal preconditioner not formed (h2_precond_blockdiag)");
-    if (o->precond == H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
+    if (o->precond >= H2_PRECOND_MLP && !h->mlp_params) return handle_fail(H2_ERR_INVALID_ARG, "no MLP attached");
     return H2_OK;
 }
 
@@ -529,6 +599,7 @@ extern "C" h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void
     if (hipHostMalloc((void**)&S.host, size_t(ncol) * kSs * 8, hipHostMallocDefault) != hipSuccess)
         return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
     S.hjend.assign(ncol, 0);
+    S.corrections.assign(ncol, 0);
     S.hlive.assign(ncol, 1);
     const double2* B = reinterpret_cast<const double2*>(b);
     double2* X = reinterpret_cast<double2*>(x);
@@ -616,6 +687,7 @@ extern "C" h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void
         r.restarts = rs[c];
         r.outer = outer[c];
         r.rel_residual = rel[c];
+        r.corrections = S.corrections[c];
         all = all && r.converged;
     }
     return all ? H2_OK : H2_NOT_CONVERGED;

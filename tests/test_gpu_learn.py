@@ -245,3 +245,54 @@ def test_resume_from_saved_iterate(torch):
     # an x0 that already solves the system returns at once
     x4, rep4 = H.gmres(bt, tol=1e-6, restart=10, x0=x3)
     assert rep4.converged and rep4.iterations == 0
+
+
+def _trained_hybrid(torch, H, g, mx, seed=9, epochs=40):
+    """An MLP (halo-free) trained on (residual, error - block-diagonal solve) pairs of random residuals."""
+    from paper_1703_01175_amd import LeafMLP
+    net = LeafMLP(mx, 64, seed=seed, zero_output=True)
+    Xs, Ts = [], []
+    for sd in range(6):
+        r = torch.from_numpy(h2gen.random_vector(3 * g.n_vox, 100 + sd)).cuda()
+        e, rep = H.gmres(r, tol=1e-10, restart=50)
+        Xs.append(H.features(r, mx))
+        Ts.append(H.targets(e - H.precond_apply(r, "blockdiag"), r, mx))
+    net.train(torch.cat(Xs), torch.cat(Ts), epochs=epochs, batch=64, lr=1e-3)
+    return net
+
+
+def test_restart_correction_matches_oracle(torch):
+    from paper_1703_01175_amd import H2Operator
+    g, d = built("cube12")
+    H = H2Operator(d, tiers=("fp64", "fp32", "bf16x3"), max_rhs=4)
+    _, mx = H.leaf_count()
+    H.precond_blockdiag()
+    net = _trained_hybrid(torch, H, g, mx)
+    H.attach_mlp(net, base="blockdiag")
+    b = h2gen.plane_wave(g, 28)[0]
+    x, rep = H.gmres(torch.from_numpy(b).cuda(), tol=1e-8, restart=4, precond="mlp_restart")
+    L = (7 * mx, 64, 6 * mx)
+    p = omlp.rounded(_split(L, net.master()))
+    xo, ro = krylov.gmres(lambda v: om.h2_matvec(d, v), b, tol=1e-8, restart=4,
+                          precond=lambda v: omlp.blockdiag_apply(d, v),
+                          correct=lambda r: omlp.apply(d, p, r, mx, on_blockdiag=True))
+    print(f"[gpu] restart correction: device {rep.iterations} its {rep.corrections} corr, "
+          f"oracle {ro.iterations} its {ro.corrections} corr", flush=True)
+    assert rep.converged and ro.converged
+    assert abs(rep.iterations - ro.iterations) <= 2 and abs(rep.corrections - ro.corrections) <= 1
+    assert rep.corrections >= 1
+    assert float(np.linalg.norm(b - om.h2_matvec(d, x.cpu().numpy())) / np.linalg.norm(b)) <= 1.0001e-8
+    # batched, BF16x3 refinement: every column converges to the FP64 tolerance
+    B = np.ascontiguousarray(h2gen.plane_wave(g, 29, count=4))
+    X, reps = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-8, restart=4, precision="bf16x3",
+                            precond="mlp_restart")
+    X = X.cpu().numpy()
+    for c in range(4):
+        assert reps[c].converged
+        assert float(np.linalg.norm(B[c] - om.h2_matvec(d, X[c])) / np.linalg.norm(B[c])) <= 1.0001e-8
+    # batched FP64 columns agree with single solves
+    X64, r64 = H.gmres_batch(torch.from_numpy(B).cuda(), tol=1e-8, restart=4, precond="mlp_restart")
+    for c in range(4):
+        _, r1 = H.gmres(torch.from_numpy(B[c]).cuda(), tol=1e-8, restart=4, precond="mlp_restart")
+        assert abs(r64[c].iterations - r1.iterations) <= 1 and abs(r64[c].corrections - r1.corrections) <= 1
+    H.close()

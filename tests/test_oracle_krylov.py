@@ -117,3 +117,23 @@ def test_givens_rotation():
         out = R @ np.array([a, b])
         assert abs(out[1]) < 1e-15 and abs(out[0] - r) < 1e-15
         assert np.allclose(R @ R.conj().T, np.eye(2), atol=1e-15)
+
+
+def test_restart_correction_special_cases():
+    """correct = exact inverse: one accepted correction solves the system with no
+    Arnoldi step; correct = 0 (never accepted) is plain GMRES step for step;
+    a harmful correction is rejected every cycle and changes nothing but the count."""
+    rng = np.random.default_rng(3)
+    n = 60
+    A = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Ainv = np.linalg.inv(A)
+    x, rep = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: Ainv @ r)
+    assert rep.converged and rep.iterations == 0 and rep.corrections == 1 and rep.matvecs == 1
+    x0, r0 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8)
+    x1, r1 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: 0 * r)
+    assert r1.corrections == 0 and r1.iterations == r0.iterations and r1.matvecs == r0.matvecs + r0.restarts
+    assert np.allclose(x1, x0, rtol=0, atol=1e-12)
+    x2, r2 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: -3.0 * r)
+    assert r2.corrections == 0 and r2.iterations == r0.iterations
+    assert np.linalg.norm(b - A @ x2) <= 1e-10 * np.linalg.norm(b)
