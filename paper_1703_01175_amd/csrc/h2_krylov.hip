@@ -23,6 +23,7 @@ namespace h2 {
 namespace {
 
 constexpr int kDotTile = 16;      // basis vectors per dot-product pass
+constexpr double kDgks = 0.70710678118654752;   // repeat Gram-Schmidt when the norm drops below this fraction
 constexpr int kDotBlocks = 512;   // partial sums per vector
 
 __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {   // conj(a) * b
@@ -332,6 +333,7 @@ struct Solver {
         return H2_OK;
     }
     int corrections = 0;
+    int reorth = 0;                    // Arnoldi steps that repeated Gram-Schmidt
 
     // GMRES(m) on Z x = rhs from x0 = 0, or from the given x when use_x0 (x overwritten).
     // prec: product tier.  Returns status; fills its/mv/restarts and the final true relative residual.
@@ -390,12 +392,20 @@ struct Solver {
                 if ((e = matvec(prec, zj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
                 ++*mv;
                 ++*its;
+                // classical Gram-Schmidt, repeated when the norm fell below 1/sqrt(2) of ||w||
+                // (the Daniel-Gragg-Kaufman-Stewart test)
+                (void)norm_into(W.w, 5);                                                   // ||w|| before
                 multidot(j + 1, W.w, W.hcol, 0);                                           // h = V^H w
-                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.hcol, -1.0, W.w, N, nullptr);
-                multidot(j + 1, W.w, W.y, 0);                                              // h' = V^H w
-                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.y, -1.0, W.w, N, W.npart);
-                k_reduce_partial<<<1, 128, 0, s>>>(W.y, 1, j + 1, W.hcol, 1);             // h += h'
-                k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);                 // ||w||
+                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.hcol, -1.0, W.w, N, W.npart);
+                k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);                 // ||w - V h||
+                if ((e = fetch(6)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                if (!(host[0] >= kDgks * host[5])) {
+                    multidot(j + 1, W.w, W.y, 0);                                          // h' = V^H w
+                    k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.y, -1.0, W.w, N, W.npart);
+                    k_reduce_partial<<<1, 128, 0, s>>>(W.y, 1, j + 1, W.hcol, 1);         // h += h'
+                    k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);             // ||w||
+                    ++reorth;
+                }
                 k_givens<<<1, 1, 0, s>>>(W.H, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal);
                 if ((e = fetch(2)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
                 jend = j + 1;

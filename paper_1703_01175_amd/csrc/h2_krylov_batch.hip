@@ -26,7 +26,9 @@ namespace {
 constexpr int kTile = 16;         // basis vectors per dot-product pass
 constexpr int kHs = 128;          // per-column stride of hcol, cs, sn, y
 constexpr int kGs = 136;          // per-column stride of g
-constexpr int kSs = 8;            // per-column stride of the scalars: 0 ||w||, 1 |g_{j+1}|, 2 ||b||, 3 ||r||
+constexpr int kSs = 8;            // per-column stride of the scalars: 0 ||w||, 1 |g_{j+1}|, 2 ||b||, 3 ||r||,
+                                  // 4 trial residual, 5 ||w|| before orthogonalisation
+constexpr double kDgks = 0.70710678118654752;   // repeat Gram-Schmidt when the norm drops below this fraction
 
 __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {   // conj(a) * b
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
@@ -38,16 +40,18 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
-// partial[c][blk][i] = this block's share of conj(V_c,i) . w_c, i in [i0, i0 + 16)
+// partial[c][blk][i] = this block's share of conj(V_c,i) . w_c, i in [i0, i0 + 16) and i < n_c
+// (n_c = nv ? nv[c] : nvec)
 __global__ __launch_bounds__(256) void kb_multidot(const double2* __restrict__ V, int64_t ldv, int64_t vs, int nvec,
-                                                   const double2* __restrict__ w, int64_t ws, int64_t N,
-                                                   double2* __restrict__ partial) {
+                                                   const int* __restrict__ nv, const double2* __restrict__ w, int64_t ws,
+                                                   int64_t N, double2* __restrict__ partial) {
     __shared__ double2 red[4][kTile];
     const int c = blockIdx.z;
     const double2* Vc = V + c * vs;
     const double2* wc = w + c * ws;
     const int i0 = blockIdx.y * kTile;
-    const int cnt = min(kTile, nvec - i0);
+    const int cnt = min(kTile, (nv ? nv[c] : nvec) - i0);
+    if (cnt <= 0) return;
     double2 acc[kTile];
 #pragma unroll
     for (int q = 0; q < kTile; ++q) acc[q] = make_double2(0, 0);
@@ -76,14 +80,15 @@ __global__ __launch_bounds__(256) void kb_multidot(const double2* __restrict__ V
     }
 }
 
-// out[c][i] (+)= sum_blk partial[c][blk][i]   (one group of 128 per column)
-__global__ void kb_reduce(const double2* __restrict__ partial, int nblk, int nvec, double2* __restrict__ out,
-                          int accumulate) {
+// out[c][i] (+)= sum_blk partial[c][blk][i] for i < n_c, 0 for n_c <= i < nvec (one group of 128 per column)
+__global__ void kb_reduce(const double2* __restrict__ partial, int nblk, int nvec, const int* __restrict__ nv,
+                          double2* __restrict__ out, int accumulate) {
     const int c = blockIdx.x, i = threadIdx.x;
     if (i >= nvec) return;
     const double2* p = partial + (int64_t)c * nblk * 128;
     double2 s = make_double2(0, 0);
-    for (int b = 0; b < nblk; ++b) { s.x += p[(int64_t)b * 128 + i].x; s.y += p[(int64_t)b * 128 + i].y; }
+    if (i < (nv ? nv[c] : nvec))
+        for (int b = 0; b < nblk; ++b) { s.x += p[(int64_t)b * 128 + i].x; s.y += p[(int64_t)b * 128 + i].y; }
     double2* o = out + (int64_t)c * kHs + i;
     if (accumulate) { s.x += o->x; s.y += o->y; }
     *o = s;
@@ -422,11 +427,12 @@ struct BSolver {
         return H2_OK;
     }
     std::vector<int> corrections;
+    int reorth = 0;                    // lockstep steps that repeated Gram-Schmidt
 
-    void multidot(int nvec, const double2* w, double2* out, int accumulate) {   // basis [j][c][ld]
+    void multidot(int nvec, const double2* w, double2* out, int accumulate, const int* nv = nullptr) {   // basis [j][c][ld]
         dim3 grid(nblk, (nvec + kTile - 1) / kTile, ncol);
-        kb_multidot<<<grid, 256, 0, s>>>(W.V, ld * ncol, ld, nvec, w, ld, N, W.dpart);
-        kb_reduce<<<ncol, 128, 0, s>>>(W.dpart, nblk, nvec, out, accumulate);
+        kb_multidot<<<grid, 256, 0, s>>>(W.V, ld * ncol, ld, nvec, nv, w, ld, N, W.dpart);
+        kb_reduce<<<ncol, 128, 0, s>>>(W.dpart, nblk, nvec, nv, out, accumulate);
     }
 
     // Restarted GMRES on Z d_c = rhs_c from d = 0 for the live columns, until
@@ -483,12 +489,28 @@ struct BSolver {
                 ++spent;
                 for (int c = 0; c < ncol; ++c)
                     if (grow[c]) { ++its[c]; ++mv[c]; }
+                // classical Gram-Schmidt; a column repeats it when its norm fell below 1/sqrt(2)
+                // of ||w|| (the Daniel-Gragg-Kaufman-Stewart test), the others keep one pass
+                norms(W.W, 5);
                 multidot(j + 1, W.W, W.hcol, 0);
-                kb_multiaxpy<<<cgrid(), 256, 0, s>>>(W.V, blk, ld, j + 1, nullptr, W.hcol, -1.0, W.W, ld, N, nullptr);
-                multidot(j + 1, W.W, W.y, 0);     // second pass (y as scratch)
-                kb_multiaxpy<<<cgrid(), 256, 0, s>>>(W.V, blk, ld, j + 1, nullptr, W.y, -1.0, W.W, ld, N, W.npart);
-                kb_reduce_add<<<ncol, 128, 0, s>>>(W.hcol, W.y, j + 1);
+                kb_multiaxpy<<<cgrid(), 256, 0, s>>>(W.V, blk, ld, j + 1, nullptr, W.hcol, -1.0, W.W, ld, N, W.npart);
                 kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 0);
+                if ((st = fetch()) != H2_OK) return st;
+                std::vector<int> again(ncol, 0);
+                bool any_again = false;
+                for (int c = 0; c < ncol; ++c)
+                    if (grow[c] && !(host[c * kSs + 0] >= kDgks * host[c * kSs + 5])) {
+                        again[c] = j + 1;
+                        any_again = true;
+                    }
+                if (any_again) {
+                    if ((st = upload_ints(W.acc, again)) != H2_OK) return st;
+                    multidot(j + 1, W.W, W.y, 0, W.acc);     // second pass (y as scratch, zeros elsewhere)
+                    kb_multiaxpy<<<cgrid(), 256, 0, s>>>(W.V, blk, ld, j + 1, W.acc, W.y, -1.0, W.W, ld, N, W.npart);
+                    kb_reduce_add<<<ncol, 128, 0, s>>>(W.hcol, W.y, j + 1);
+                    kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 0);
+                    ++reorth;
+                }
                 kb_givens<<<ncol, 64, 0, s>>>(W.H, int64_t(m + 1) * m, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal);
                 if ((st = fetch()) != H2_OK) return st;
                 bool more = false;
