@@ -264,8 +264,8 @@ def batched(args):
     from h2gen.desc import H2Desc
 
     t0 = time.time()
-    edge, side, eps_r, seed, eps = WORKLOADS["cube64"]
-    g = h2gen.cube(edge, side, eps_r, seed=seed, name="cube64")
+    edge, side, eps_r, seed, eps = WORKLOADS[args.workload]
+    g = h2gen.cube(edge, side, eps_r, seed=seed, name=args.workload)
     if args.cache and os.path.exists(os.path.join(args.cache, "desc.json")):
         d = H2Desc.load_dir(args.cache)
     else:
@@ -350,7 +350,7 @@ def batched(args):
         "value": round(n_rhs_total / (ms * 1e-3), 2), "unit": "RHS-products/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 (fp32 accumulate)", "data": "synthetic",
-        "config": {"workload": f"64^3 cube x 256 plane waves + {len(sd)} uneven cubes (edges "
+        "config": {"workload": f"{edge}^3 cube x 256 plane waves + {len(sd)} uneven cubes (edges "
                                f"{sorted(int(x.shape[0]) for x in smalls)}) x 1 plane wave", "tile": tile},
         "fp64_single_rhs_ms": round(ms64, 3),
         "speedup_per_rhs_vs_fp64": round((ms64 * n_rhs_total) / ms, 2),
