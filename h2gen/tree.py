@@ -2,7 +2,7 @@
 
 The computational domain is split recursively until a cluster holds at most
 `leaf_size` voxels.  The paper splits into two balanced halves; on voxel boxes
-this build splits a box at the midpoint (first half ceil(n/2)) of every axis
+the tree here splits a box at the midpoint (first half ceil(n/2)) of every axis
 whose extent is at least longest/sqrt(2).  That gives 8 children on cubes (an
 octree), 4 on 2:1 slabs and 2 on rods, all balanced.
 

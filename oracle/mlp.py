@@ -1,8 +1,8 @@
 """Per-leaf MLP preconditioner, FP64 reference (test infrastructure).
 
-The learned part is this build's own: the paper has no network (the
-configuration asks for one).  One MLP with weights shared by every leaf
-cluster maps a leaf's residual to a leaf correction:
+The network is not from the paper, which has none; it is the learned
+preconditioner added around the method.  One MLP with weights shared by every
+leaf cluster maps a leaf's residual to a leaf correction:
 
     h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  y = W3 h2 + b3,
 

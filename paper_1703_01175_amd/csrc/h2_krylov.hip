@@ -275,8 +275,15 @@ struct Solver {
         if (prec == 0) return launch_matvec(*d, *lv, 1, 0, x, y, 1, N, s);
         hipError_t e = launch_vec_to_fp32(x, W.lo_in, N, s);
         if (e != hipSuccess) return e;
-        e = launch_matvec(*d, *lv, 1, prec, W.lo_in, W.lo_out, 1, N, s);
-        if (e != hipSuccess) return e;
+        if (prec == H2_BF16X3) {   // the batched tier's group holding this handle alone, one column
+            const void* xin[1] = {W.lo_in};
+            void* yout[1] = {W.lo_out};
+            const int64_t nr[1] = {1}, lds[1] = {N};
+            if (group_run(h->self_group, 1, xin, yout, nr, lds, s) != H2_OK) return hipErrorLaunchFailure;
+        } else {
+            e = launch_matvec(*d, *lv, 1, prec, W.lo_in, W.lo_out, 1, N, s);
+            if (e != hipSuccess) return e;
+        }
         return launch_vec_to_fp64(W.lo_out, y, N, s);
     }
 
@@ -455,7 +462,8 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
         return handle_fail(H2_ERR_INVALID_ARG, "misaligned vector");
     const DevH2* d = handle_dev(h);
     if (!d->has_tier[o->precision]) return handle_fail(H2_ERR_INVALID_ARG, "precision tier was not built");
-    if (o->precision == H2_BF16X3) return handle_fail(H2_ERR_INVALID_ARG, "BF16X3 product is not available in this build");
+    if (o->precision == H2_BF16X3 && (!h->self_group || !h->batch))
+        return handle_fail(H2_ERR_INVALID_ARG, "BF16X3 tier was not built");
     if (o->precond < H2_PRECOND_NONE || o->precond > H2_PRECOND_MLP_RESTART)
         return handle_fail(H2_ERR_INVALID_ARG, "unknown preconditioner");
     if (o->precond == H2_PRECOND_BLOCKDIAG && !h->bd_ready)

@@ -63,6 +63,22 @@ def test_gmres_ir_fp32(torch):
     assert _true_res(d, x.cpu().numpy(), b) <= 1.0001e-6
 
 
+def test_gmres_ir_bf16x3_single_rhs(torch):
+    """BF16x3 products (matrix cores, one column) inside the refinement of a single solve."""
+    from paper_1703_01175_amd import H2Operator
+    g, d = built("cube12")
+    H = H2Operator(d, tiers=("fp64", "bf16x3"), max_rhs=1)
+    b = h2gen.plane_wave(g, 5)[0]
+    x, rep = H.gmres(torch.from_numpy(b).cuda(), tol=1e-9, precision="bf16x3", inner_tol=1e-3)
+    assert rep.converged and rep.outer >= 2
+    assert _true_res(d, x.cpu().numpy(), b) <= 1.0001e-9
+    H.close()
+    # without the tier the request is refused
+    _, _, H64 = operator("cube12")
+    with pytest.raises(Exception):
+        H64.gmres(torch.from_numpy(b).cuda(), precision="bf16x3")
+
+
 def test_gmres_zero_rhs(torch):
     g, d, H = operator("rod")
     b = torch.zeros(3 * g.n_vox, dtype=torch.complex128, device="cuda")
