@@ -48,6 +48,7 @@ h2_status group_create(const h2_handle* hs, int n, void* mem, size_t bytes, hipS
 h2_status group_run(h2_group g, int op, const void* const* x, void* const* y, const int64_t* n_rhs,
                     const int64_t* ld, hipStream_t s);
 void group_destroy(h2_group g);
+h2_status group_autotile(h2_group g, const void* x, void* y, int64_t n_rhs, int64_t ld, hipStream_t s);
 
 // Event pairs around kernel families; read back (and summed) on demand.
 struct EventProfiler : Profiler {

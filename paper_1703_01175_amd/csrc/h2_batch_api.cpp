@@ -216,6 +216,7 @@ struct h2_group_s {
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::string cols_key;           // column configuration the task lists were built for
+    std::map<int64_t, int> tile_for_rhs;   // tiles tuned inside solves, by right-hand-side count
     ~h2_group_s();
 };
 
@@ -621,3 +622,31 @@ h2_status h2_group_set(h2_group g, int32_t tile, int32_t use_graph) {
 void h2_group_destroy(h2_group g) { group_destroy(g); }
 
 }  // extern "C"
+
+namespace h2 {
+
+// Tile for a single-member group at n_rhs right-hand sides: tuned on first use
+// (timing the three tiles on the given buffers, whose values do not matter),
+// then reused.  Used by the solvers before their first product.
+h2_status group_autotile(h2_group g, const void* x, void* y, int64_t n_rhs, int64_t ld, hipStream_t s) {
+    if (!group_ok(g)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid group");
+    auto it = g->tile_for_rhs.find(n_rhs);
+    if (it != g->tile_for_rhs.end()) {
+        if (g->nc != it->second) {
+            g->nc = it->second;
+            drop_graph(g);
+            g->cols_key.clear();
+        }
+        return H2_OK;
+    }
+    const void* xs[1] = {x};
+    void* ys[1] = {y};
+    const int64_t nr[1] = {n_rhs}, lds[1] = {ld};
+    int32_t tile = 0;
+    h2_status st = h2_group_tune(g, H2_OP_Z, xs, ys, nr, lds, s, &tile);
+    if (st != H2_OK) return st;
+    g->tile_for_rhs[n_rhs] = tile;
+    return H2_OK;
+}
+
+}  // namespace h2

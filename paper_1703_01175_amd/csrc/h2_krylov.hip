@@ -485,6 +485,12 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     S.nblk = int(std::min<int64_t>(kDotBlocks, (N + 255) / 256));
     work_layout(N, m, &S.W, base, pc, d->leaves.n, h->mlp_dims.n_in, h->mlp_dims.n_hidden, h->mlp_dims.n_out);
     S.precond = pc;
+    if (o->precision == H2_BF16X3) {   // block-GEMM tile for one column (tuned once)
+        if (hipMemsetAsync(S.W.lo_in, 0, size_t(N) * 8, S.s) != hipSuccess)
+            return handle_fail(H2_ERR_DEVICE, "workspace clear failed");
+        h2_status ts = group_autotile(h->self_group, S.W.lo_in, S.W.lo_out, 1, N, S.s);
+        if (ts != H2_OK) return ts;
+    }
     if (hipHostMalloc((void**)&S.host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
     *rep = h2_gmres_report{};

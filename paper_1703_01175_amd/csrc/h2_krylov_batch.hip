@@ -633,6 +633,11 @@ extern "C" h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void
     auto run = [&]() -> h2_status {
         h2_status st2;
         const dim3 cg = S.cgrid();
+        if (prec == H2_BF16X3) {   // block-GEMM tile for this column count (tuned once per count)
+            if (hipMemsetAsync(S.W.lo_in, 0, size_t(ld) * ncol * 8, S.s) != hipSuccess)
+                return handle_fail(H2_ERR_DEVICE, "workspace clear failed");
+            if ((st2 = group_autotile(h->self_group, S.W.lo_in, S.W.lo_out, ncol, ld, S.s)) != H2_OK) return st2;
+        }
         S.norms(B, 2);
         if ((st2 = S.fetch()) != H2_OK) return st2;
         for (int c = 0; c < ncol; ++c) {
