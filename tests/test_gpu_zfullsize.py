@@ -3,7 +3,9 @@
 The representation is built on the host (about two minutes on a 16-core host),
 then the GPU product in the configuration bench.py times is compared with the
 full oracle product on the same representation, and a GMRES(50) solve is judged
-by the oracle's FP64 residual.
+by the oracle's FP64 residual.  The batched BF16x3 product in its benchmark
+configuration (256 plane waves, tile autotuned) is compared with the oracle on
+sampled right-hand sides.
 """
 import time
 
@@ -30,7 +32,7 @@ def full(capsys):
             print("\n[fullsize] building the 64^3 representation on the host", flush=True)
             g = h2gen.cube(64, 4.0, (2.0, 6.0), seed=2, name="cube64")
             d = build_h2(g, eps=1e-3, verbose=True)
-            H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0")
+            H = H2Operator(d, tiers=("fp64", "fp32", "bf16x3"), max_rhs=256, device="cuda:0")
         _FULL["op"] = (g, d, H)
     return _FULL["op"]
 
@@ -70,3 +72,26 @@ def test_cube64_gmres_residual_by_oracle(full, capsys):
         print(f"[fullsize] GMRES {rep.iterations} its, device residual {rep.rel_residual:.2e}, oracle {res:.2e}",
               flush=True)
     assert rep.converged and res <= 1.0001e-6
+
+
+def test_cube64_batched_bf16x3_sampled_against_oracle(full, capsys):
+    import torch
+    import h2gen
+    from oracle import matvec as om
+    from paper_1703_01175_amd import H2Group
+    g, d, H = full
+    B = h2gen.plane_wave(g, 4, count=256)
+    grp = H2Group([H])
+    xs = [torch.from_numpy(B.astype(np.complex64)).cuda()]
+    outs = [torch.empty_like(xs[0])]
+    tile = grp.tune(xs, outs=outs)
+    grp.matvec(xs, outs=outs)
+    Y = outs[0]
+    errs = []
+    for r in (0, 131, 255):
+        yo = om.h2_matvec(d, B[r])
+        errs.append(float(np.linalg.norm(Y[r].cpu().numpy() - yo) / np.linalg.norm(yo)))
+    with capsys.disabled():
+        print(f"[fullsize] BF16x3 x 256 RHS (tile {tile}): rel err vs oracle {errs}", flush=True)
+    assert max(errs) <= 1e-5
+    grp.close()
