@@ -202,6 +202,7 @@ __global__ __launch_bounds__(64) void k_leaf_means(int nleaf, const int* __restr
                                                    const double* __restrict__ norm, double sqrtN, float* __restrict__ means) {
     __shared__ double red[6][64];
     const int t = blockIdx.x;
+    if (t >= nleaf) return;                   // uniform over the group, before any barrier
     const int n = lsize[t], b = lbeg[t];
     const int i = threadIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};
@@ -296,6 +297,7 @@ __global__ __launch_bounds__(256) void k_bd_setup(int nleaf, const int* __restri
     __shared__ int piv;
     __shared__ double2 dinv_s;
     const int t = blockIdx.x;
+    if (t >= nleaf) return;                   // uniform over the group, before any barrier
     const int n = lsize[t], b = lbeg[t];
     const double2* G = near + ldiag[t];
     double2* A = aug_all + loff[t];          // A(i, j) = A[i + j n], j < 2n
@@ -368,6 +370,7 @@ __global__ __launch_bounds__(64) void k_bd_apply(int nleaf, const int* __restric
                                                  double2* __restrict__ z) {
     __shared__ double2 rs[64 * 3];
     const int t = blockIdx.x;
+    if (t >= nleaf) return;
     const int n = lsize[t], b = lbeg[t];
     for (int e = threadIdx.x; e < 3 * n; e += 64) rs[e] = r[(int64_t)perm[b + e / 3] * 3 + e % 3];
     __syncthreads();
