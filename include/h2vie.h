@@ -340,10 +340,11 @@ h2_status h2_group_build(const h2_handle* members, int32_t n, void* dev_buffer, 
 h2_status h2_group_matvec(h2_group g, h2_op op, const void* const* x, void* const* y, const int64_t* n_rhs,
                           const int64_t* ld, void* stream);
 /* Autotuner: times the column tile widths 32, 64 and 128 of the block GEMM on the
- * given vectors and keeps the fastest (written to *tile).  Synchronises. */
+ * given vectors, phase by phase, and keeps each phase's fastest (*tile receives the
+ * near-field phase's).  Synchronises. */
 h2_status h2_group_tune(h2_group g, h2_op op, const void* const* x, void* const* y, const int64_t* n_rhs,
                         const int64_t* ld, void* stream, int32_t* tile);
-/* Set the column tile (32, 64, 128; 0 keeps it) and graph use (0 / 1). */
+/* Set the column tile of every phase (32, 64, 128; 0 keeps the tiles) and graph use (0 / 1). */
 h2_status h2_group_set(h2_group g, int32_t tile, int32_t use_graph);
 void h2_group_destroy(h2_group g);
 

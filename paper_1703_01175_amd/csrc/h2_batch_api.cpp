@@ -208,6 +208,7 @@ struct h2_group_s {
     std::vector<h2::GroupDev> dev;
     int n_up = 0, n_down = 0;
     int nc = 64;                    // column tile of the block GEMM (autotuned)
+    std::vector<int> nc_phase;      // per-phase tiles chosen by the tuner (empty: nc everywhere)
     bool use_graph = true;
     // graph cache
     hipGraphExec_t exec = nullptr;
@@ -216,7 +217,7 @@ struct h2_group_s {
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::string cols_key;           // column configuration the task lists were built for
-    std::map<int64_t, int> tile_for_rhs;   // tiles tuned inside solves, by right-hand-side count
+    std::map<int64_t, std::vector<int>> tile_for_rhs;   // per-phase tiles tuned inside solves, by RHS count
     ~h2_group_s();
 };
 
@@ -361,9 +362,14 @@ static hipError_t group_upload(h2_group g, hipStream_t s) {
     return hipStreamSynchronize(s);
 }
 
+static int phase_tile(h2_group g, size_t phase) {
+    return phase < g->nc_phase.size() ? g->nc_phase[phase] : g->nc;
+}
+
 // Task lists (owner, first column) for the current column counts.
 static hipError_t group_tasks(h2_group g, hipStream_t s) {
     std::string key = std::to_string(g->nc);
+    for (int t : g->nc_phase) key += "/" + std::to_string(t);
     for (auto& m : g->members) key += "," + std::to_string(m.ncols);
     if (key == g->cols_key) return hipSuccess;
     for (size_t i = 0; i < g->host.size(); ++i) {
@@ -374,7 +380,7 @@ static hipError_t group_tasks(h2_group g, hipStream_t s) {
         for (size_t o = 0; o < G.owners.size(); ++o) {
             const int cols = g->members[G.owner_member[o]].ncols;
             ocols[o] = cols;
-            for (int c0 = 0; c0 < cols; c0 += g->nc) tasks.push_back(make_int2(int(o), c0));
+            for (int c0 = 0; c0 < cols; c0 += phase_tile(g, i)) tasks.push_back(make_int2(int(o), c0));
         }
         std::vector<int> scols;
         int64_t mx = 0;
@@ -404,9 +410,10 @@ static hipError_t group_tasks(h2_group g, hipStream_t s) {
     return e;
 }
 
-// The whole batched product of every member, phase by phase.
+// The whole batched product of every member, phase by phase.  ev (optional, two
+// events per phase) brackets each phase's block GEMM for the tuner.
 static hipError_t group_launch(h2_group g, int op, const void* const* x, void* const* y, const int64_t* ld,
-                               hipStream_t s) {
+                               hipStream_t s, const std::vector<hipEvent_t>* ev = nullptr) {
     hipError_t e;
     for (size_t mi = 0; mi < g->members.size(); ++mi) {
         const GroupMember& m = g->members[mi];
@@ -418,7 +425,10 @@ static hipError_t group_launch(h2_group g, int op, const void* const* x, void* c
     }
     for (size_t i = 0; i < g->host.size(); ++i) {
         GroupDev& P = g->dev[i];
-        if ((e = launch_bgemm(g->nc, P.owners, P.terms, P.tasks, P.n_tasks, P.owner_cols, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord((*ev)[2 * i], s)) != hipSuccess) return e;
+        if ((e = launch_bgemm(phase_tile(g, i), P.owners, P.terms, P.tasks, P.n_tasks, P.owner_cols, s)) != hipSuccess)
+            return e;
+        if (ev && (e = hipEventRecord((*ev)[2 * i + 1], s)) != hipSuccess) return e;
         if ((e = launch_split(P.splits, P.n_splits, int(std::min<int64_t>(P.max_split_elems, 1 << 30)),
                               P.split_cols, s)) != hipSuccess)
             return e;
@@ -587,32 +597,57 @@ h2_status h2_group_tune(h2_group g, h2_op op, const void* const* x, void* const*
     if (!tile) return handle_fail(H2_ERR_INVALID_ARG, "null tile output");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int cand[3] = {32, 64, 128};
-    double best = 1e300;
-    int best_nc = g->nc;
+    const size_t np = g->host.size();
+    std::vector<hipEvent_t> ev(2 * np, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return handle_fail(H2_ERR_DEVICE, "event creation failed");
+        }
+    auto release = [&]() {
+        for (auto& f : ev) (void)hipEventDestroy(f);
+    };
+    // every phase's block GEMM timed at every tile width (three products each); each phase keeps its fastest
+    std::vector<double> best(np, 1e300);
+    std::vector<int> pick(np, g->nc);
     const bool graph = g->use_graph;
     g->use_graph = false;
     for (int c : cand) {
         g->nc = c;
+        g->nc_phase.clear();
         h2_status st = group_run(g, int(op), x, y, n_rhs, ld, s);   // warm-up (also builds the task lists)
-        if (st != H2_OK) { g->use_graph = graph; return st; }
-        if (hipStreamSynchronize(s) != hipSuccess) { g->use_graph = graph; return handle_fail(H2_ERR_DEVICE, "sync failed"); }
-        auto t0 = std::chrono::steady_clock::now();
-        for (int r = 0; r < 3; ++r) (void)group_run(g, int(op), x, y, n_rhs, ld, s);
-        if (hipStreamSynchronize(s) != hipSuccess) { g->use_graph = graph; return handle_fail(H2_ERR_DEVICE, "sync failed"); }
-        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (dt < best) { best = dt; best_nc = c; }
+        if (st != H2_OK) { g->use_graph = graph; release(); return st; }
+        std::vector<double> t(np, 0.0);
+        for (int r = 0; r < 3; ++r) {
+            hipError_t e = group_launch(g, int(op), x, y, ld, s, &ev);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { g->use_graph = graph; release(); return handle_fail(H2_ERR_DEVICE, "tuning run failed"); }
+            for (size_t i = 0; i < np; ++i) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) t[i] += ms;
+            }
+        }
+        for (size_t i = 0; i < np; ++i)
+            if (t[i] < best[i]) { best[i] = t[i]; pick[i] = c; }
     }
+    release();
     g->use_graph = graph;
-    g->nc = best_nc;
+    g->nc = np ? pick[np - 1] : 64;      // the near-field phase's tile, reported
+    g->nc_phase = pick;
     drop_graph(g);
-    *tile = best_nc;
+    g->cols_key.clear();
+    *tile = g->nc;
     return H2_OK;
 }
 
 h2_status h2_group_set(h2_group g, int32_t tile, int32_t use_graph) {
     if (!group_ok(g)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid group");
     if (tile != 0 && tile != 32 && tile != 64 && tile != 128) return handle_fail(H2_ERR_INVALID_ARG, "tile must be 32, 64 or 128");
-    if (tile) g->nc = tile;
+    if (tile) {
+        g->nc = tile;
+        g->nc_phase.clear();
+    }
     g->use_graph = use_graph != 0;
     drop_graph(g);
     g->cols_key.clear();
@@ -632,8 +667,8 @@ h2_status group_autotile(h2_group g, const void* x, void* y, int64_t n_rhs, int6
     if (!group_ok(g)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid group");
     auto it = g->tile_for_rhs.find(n_rhs);
     if (it != g->tile_for_rhs.end()) {
-        if (g->nc != it->second) {
-            g->nc = it->second;
+        if (g->nc_phase != it->second) {
+            g->nc_phase = it->second;
             drop_graph(g);
             g->cols_key.clear();
         }
@@ -645,7 +680,7 @@ h2_status group_autotile(h2_group g, const void* x, void* y, int64_t n_rhs, int6
     int32_t tile = 0;
     h2_status st = h2_group_tune(g, H2_OP_Z, xs, ys, nr, lds, s, &tile);
     if (st != H2_OK) return st;
-    g->tile_for_rhs[n_rhs] = tile;
+    g->tile_for_rhs[n_rhs] = g->nc_phase;
     return H2_OK;
 }
 
