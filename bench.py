@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--solve-tiers", default="bf16x3,fp32,fp64", help="product tiers of --solve-batch")
     ap.add_argument("--solve-single", type=int, default=4, help="FP64 single-RHS solves timed by --solve-batch")
     ap.add_argument("--restart", type=int, default=30, help="restart length of the batched solves")
+    ap.add_argument("--product-only", action="store_true", help="--solve-batch: time the FP64 products and stop")
     ap.add_argument("--learned", action="store_true",
                     help="learned-preconditioner experiment on the layered slab (pairs, training, FGMRES)")
     ap.add_argument("--slab", default="96x96x48", help="slab voxels for --learned")
@@ -556,6 +557,30 @@ def solve_batch(args):
         return out
 
     res = {}
+    # the FP64 product itself: n right-hand sides in passes of four against one at a time
+    Yp = torch.empty_like(B)
+    H.matvec(B, out=Yp)
+    sync()
+    t0 = time.time()
+    for _ in range(3):
+        H.matvec(B, out=Yp)
+    sync()
+    multi_ms = (time.time() - t0) / 3 / n * 1e3
+    y1 = torch.empty_like(B[0])
+    t0 = time.time()
+    for _ in range(3):
+        H.matvec(B[0], out=y1)
+    sync()
+    single_ms = (time.time() - t0) / 3 * 1e3
+    res["fp64_product"] = {"multi_rhs_ms_per_rhs": round(multi_ms, 3), "single_rhs_ms": round(single_ms, 3)}
+    log(f"[solve] fp64 product: {multi_ms:.2f} ms per rhs in passes of four, {single_ms:.2f} ms alone")
+    if args.product_only:
+        print(json.dumps({"metric": "fp64_product_ms_per_rhs", "value": round(multi_ms, 3), "unit": "ms",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "cube64", "n_rhs": n}, "single_rhs_ms": round(single_ms, 3)}),
+              flush=True)
+        H.close()
+        return
     # plain FP64, one right-hand side at a time
     k = max(1, min(args.solve_single, n))
     H.gmres(B[0], tol=1e-6, restart=50, max_matvec=60)       # warm-up

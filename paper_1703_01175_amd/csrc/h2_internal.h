@@ -9,6 +9,8 @@ namespace h2 {
 
 constexpr int kNcomp = 3;        // field components per voxel
 constexpr int kMaxLeaf = 64;     // voxels per leaf cluster
+constexpr int kMrRhs = 4;        // right-hand sides per pass of the multi-RHS FP64 / FP32 product
+constexpr int kMrCols = kNcomp * kMrRhs;
 constexpr int kMaxRank = 256;    // cluster rank limit
 
 // Storage tier of the block data (near blocks, couplings, bases, transfers).
@@ -82,7 +84,8 @@ struct DevH2 {
     TierData tier[3];
     bool has_tier[3] = {true, false, false};
 
-    // scratch for one product (3 * max_rhs columns)
+    // scratch for one product pass (vec_cols columns: 3, or kMrCols when built with max_rhs >= 2)
+    int vec_cols = kNcomp;
     void* U = nullptr;                  // [n_vox][ncols] tree order, vector type
     void* Xh = nullptr;                 // [coef_rows][ncols]
     void* Yh = nullptr;                 // [coef_rows][ncols]
@@ -106,5 +109,9 @@ struct Profiler {
 // n_rhs passes of 3; x/y have leading dimension ld (complex elements).
 hipError_t launch_matvec(const DevH2& d, const LevelLaunch& lv, int op, int prec, const void* x,
                          void* y, int64_t n_rhs, int64_t ld, hipStream_t s, Profiler* prof = nullptr);
+// Several right-hand sides: passes of kMrRhs through the multi-RHS kernels
+// (h2_matvec_mr.hip) when the scratch holds kMrCols columns, else launch_matvec.
+hipError_t launch_matvec_multi(const DevH2& d, const LevelLaunch& lv, int op, int prec, const void* x, void* y,
+                               int64_t n_rhs, int64_t ld, hipStream_t s);
 
 }  // namespace h2

@@ -339,13 +339,13 @@ struct BSolver {
     h2_status prod(int prec, const double2* x, double2* y) {
         hipError_t e;
         if (prec == H2_FP64) {
-            e = launch_matvec(*d, *lv, 1, 0, x, y, ncol, ld, s);
+            e = launch_matvec_multi(*d, *lv, 1, 0, x, y, ncol, ld, s);
             return e == hipSuccess ? H2_OK : handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         }
         const int64_t flat = ld * ncol;
         if ((e = launch_vec_to_fp32(x, W.lo_in, flat, s)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         if (prec == H2_FP32) {
-            e = launch_matvec(*d, *lv, 1, 1, W.lo_in, W.lo_out, ncol, ld, s);
+            e = launch_matvec_multi(*d, *lv, 1, 1, W.lo_in, W.lo_out, ncol, ld, s);
             if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         } else {
             const void* xin[1] = {W.lo_in};

@@ -72,6 +72,7 @@ struct Plan {
     size_t group_bytes = 0;
     ~Plan() { delete batch; }
     size_t o_U, o_X, o_Y, o_aux;
+    int vec_cols = kNcomp;
     size_t aux_bytes = 0;
     Layout lay;
 };
@@ -351,7 +352,8 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         P.group_bytes = group_need_batch(&B);
         P.o_group = L.add(P.group_bytes);
     }
-    const size_t cols = size_t(kNcomp);
+    const size_t cols = size_t(o->max_rhs >= 2 ? kMrCols : kNcomp);   // multi-RHS passes need kMrCols
+    P.vec_cols = int(cols);
     P.o_U = L.add(size_t(n) * cols * 16);
     P.o_X = L.add(size_t(std::max(P.coef_rows, 1)) * cols * 16);
     P.o_Y = L.add(size_t(std::max(P.coef_rows, 1)) * cols * 16);
@@ -524,6 +526,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         }
     }
     D.U = base + P.o_U;
+    D.vec_cols = P.vec_cols;
     D.Xh = base + P.o_X;
     D.Yh = base + P.o_Y;
     h->aux = base + P.o_aux;
@@ -589,8 +592,11 @@ h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* 
         const int64_t nr[1] = {n_rhs}, lds[1] = {ld};
         return group_run(h->self_group, int(op), xs, ys, nr, lds, reinterpret_cast<hipStream_t>(stream));
     }
-    hipError_t e = launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld, reinterpret_cast<hipStream_t>(stream),
-                                 h->prof);
+    hipError_t e = (n_rhs > 1 && !h->prof)
+                       ? launch_matvec_multi(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld,
+                                             reinterpret_cast<hipStream_t>(stream))
+                       : launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld,
+                                       reinterpret_cast<hipStream_t>(stream), h->prof);
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "matvec launch failed: %s", hipGetErrorString(e));
     return H2_OK;
 }
