@@ -203,6 +203,17 @@ def main():
                                           converged=rep.converged, rel_residual=rep.rel_residual)
             log(f"[bench] GMRES {prec}: {dt:.3f}s, {rep.iterations} its, {rep.matvecs} products, "
                 f"residual {rep.rel_residual:.2e}")
+        bt = torch.from_numpy(b_np).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, rep = H.bicgstab(bt, tol=1e-6)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        extra["bicgstab_fp64"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
+                                      iterations=rep.iterations, matvecs=rep.matvecs, converged=rep.converged,
+                                      rel_residual=rep.rel_residual)
+        log(f"[bench] BiCGStab fp64: {dt:.3f}s, {rep.iterations} steps, {rep.matvecs} products, "
+            f"residual {rep.rel_residual:.2e}")
 
     cpu = None
     parity = None

@@ -198,6 +198,17 @@ h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes)
 h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h2_gmres_opts* o,
                          h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
 
+/* Solve Z x = b by BiCGStab (van der Vorst), the iterative method of the paper's
+ * experiments (Sec. V), in FP64 on the device: x0 = 0, shadow residual b,
+ * deterministic reductions, two products per step; stops when ||s|| or ||r||
+ * reaches tol * ||b|| (or on breakdown) and reports the true FP64 residual
+ * b - Z x (rep->restarts = rep->outer = 0).  b, x: device complex double,
+ * length N; work: h2_bicgstab_workspace bytes.  Synchronises the stream.
+ * Returns OK, NOT_CONVERGED (x holds the last iterate) or an error. */
+h2_status h2_bicgstab_workspace(h2_handle h, size_t* bytes);
+h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
+                            h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
+
 /* Solve Z x_c = b_c for n_rhs right-hand sides at once (the paper's many
  * right-hand sides, Sec. IV.D): every column runs its own restarted GMRES (FP64
  * Arnoldi, CGS2, Givens, own basis and Hessenberg matrix) in lockstep with the

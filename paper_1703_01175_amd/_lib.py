@@ -98,6 +98,10 @@ def load() -> C.CDLL:
     lib.h2_gmres_solve_batch.restype = C.c_int
     lib.h2_gmres_solve_batch.argtypes = [vp, C.c_int64, vp, vp, C.c_int64, C.POINTER(GmresOpts),
                                          C.POINTER(GmresReport), vp, sz, vp]
+    lib.h2_bicgstab_workspace.restype = C.c_int
+    lib.h2_bicgstab_workspace.argtypes = [vp, C.POINTER(sz)]
+    lib.h2_bicgstab_solve.restype = C.c_int
+    lib.h2_bicgstab_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int32, C.POINTER(GmresReport), vp, sz, vp]
     lib.h2_stats.restype = C.c_int
     lib.h2_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.h2_group_plan.restype = C.c_int

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libh2vie.so")
-SOURCES = ["h2vie_api.cpp", "h2_matvec.hip", "h2_convert.hip", "h2_krylov.hip", "h2_batch.hip", "h2_batch_api.cpp", "h2_learn.hip", "h2_krylov_batch.hip", "h2_matvec_mr.hip"]
+SOURCES = ["h2vie_api.cpp", "h2_matvec.hip", "h2_convert.hip", "h2_krylov.hip", "h2_batch.hip", "h2_batch_api.cpp", "h2_learn.hip", "h2_krylov_batch.hip", "h2_matvec_mr.hip", "h2_bicgstab.hip"]
 ARCH = os.environ.get("H2VIE_ARCH", "gfx950")
 
 

@@ -137,3 +137,19 @@ def test_restart_correction_special_cases():
     x2, r2 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: -3.0 * r)
     assert r2.corrections == 0 and r2.iterations == r0.iterations
     assert np.linalg.norm(b - A @ x2) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_bicgstab_against_scipy_iterations():
+    """Same method as scipy's BiCGStab (shadow residual b, x0 = 0): the step counts
+    to the tolerance agree within one and the iterates reach the same solution."""
+    import scipy.sparse.linalg as spla
+    Z, g = _vie_matrix()
+    b = h2gen.random_vector(Z.shape[0], 14)
+    x, rep = krylov.bicgstab(lambda v: Z @ v, b, tol=1e-10)
+    steps = []
+    xs, info = spla.bicgstab(Z, b, rtol=1e-10, atol=0.0, maxiter=500, callback=lambda xk: steps.append(1))
+    assert rep.converged and info == 0
+    assert abs(rep.iterations - len(steps)) <= 1
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    # two products per full step, one more for the closing true residual
+    assert rep.matvecs <= 2 * rep.iterations + 1
