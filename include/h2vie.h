@@ -287,7 +287,9 @@ h2_status h2_leaf_features(h2_handle h, int32_t n_pad, const void* r, float* X, 
 h2_status h2_leaf_targets(h2_handle h, int32_t n_pad, const void* e, const void* r, float* T, void* scratch,
                           void* stream);
 h2_status h2_precond_blockdiag_bytes(h2_handle h, size_t* bytes);
-/* Form the leaf inverses into buf; INVALID_ARG if a leaf block is singular. Synchronises. */
+/* Form the leaf inverses into buf; INVALID_ARG if a leaf block is singular. Synchronises.
+ * buf (caller memory) is read by every later BLOCKDIAG application and by an MLP
+ * attached with that base: keep it alive, unchanged, while the handle uses them. */
 h2_status h2_precond_blockdiag(h2_handle h, void* buf, size_t bytes, void* stream);
 /* Attach an MLP (parameters stay caller owned) for PRECOND_MLP solves.  base:
  * PRECOND_NONE (z = MLP output) or PRECOND_BLOCKDIAG (z = block-diagonal solve
