@@ -118,13 +118,25 @@ __global__ void k_loss_finish(const float* __restrict__ part, int nb, int n, flo
     *loss = float(0.5 * s / n);
 }
 
-// db[j] = sum_i dY[i][j]
-__global__ void k_colsum(const float* __restrict__ D, int n, int m, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+// db[j] = sum_i dY[i][j]: 64 columns per group, its 16 waves take every 16th row (each
+// wave reads 64 consecutive floats of a row), then the 16 partial sums add through LDS
+// in a fixed order
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ D, int n, int m, float* __restrict__ out) {
+    __shared__ float red[16][64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + l;
     float s = 0.f;
-    for (int i = 0; i < n; ++i) s += D[(int64_t)i * m + j];
-    out[j] = s;
+    if (j < m) {
+#pragma unroll 8
+        for (int i = w; i < n; i += 16) s += D[(int64_t)i * m + j];
+    }
+    red[w][l] = s;
+    __syncthreads();
+    if (w == 0 && j < m) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k][l];
+        out[j] = t;
+    }
 }
 
 // gather rows: X[i] = src[idx[i]]
@@ -484,16 +496,16 @@ void mlp_grad_dev(const MlpLayout& L, void* params, const float* X, const float*
     float* g = W.grad;
     // layer 3: dW3 = dY^T H2, db3 = colsum dY
     gemm<float, float>(s, L.n_out, L.h, int(n), W.dY, 1, L.n_out, W.H2, L.h, 1, g + L.w3, L.h, nullptr, 0, nullptr, 0, 0);
-    k_colsum<<<(L.n_out + 255) / 256, 256, 0, s>>>(W.dY, int(n), L.n_out, g + L.b3);
+    k_colsum<<<(L.n_out + 63) / 64, 1024, 0, s>>>(W.dY, int(n), L.n_out, g + L.b3);
     // dH2 = (dY W3) * (H2 > 0)
     gemm<float, uint16_t>(s, int(n), L.h, L.n_out, W.dY, L.n_out, 1, P.bf + L.w3, L.h, 1, W.dH2, L.h, nullptr, 0, W.H2,
                           L.h, 0);
     gemm<float, float>(s, L.h, L.h, int(n), W.dH2, 1, L.h, W.H1, L.h, 1, g + L.w2, L.h, nullptr, 0, nullptr, 0, 0);
-    k_colsum<<<(L.h + 255) / 256, 256, 0, s>>>(W.dH2, int(n), L.h, g + L.b2);
+    k_colsum<<<(L.h + 63) / 64, 1024, 0, s>>>(W.dH2, int(n), L.h, g + L.b2);
     // dH1 = (dH2 W2) * (H1 > 0)
     gemm<float, uint16_t>(s, int(n), L.h, L.h, W.dH2, L.h, 1, P.bf + L.w2, L.h, 1, W.dH1, L.h, nullptr, 0, W.H1, L.h, 0);
     gemm<float, float>(s, L.h, L.n_in, int(n), W.dH1, 1, L.h, Xb, L.n_in, 1, g + L.w1, L.n_in, nullptr, 0, nullptr, 0, 0);
-    k_colsum<<<(L.h + 255) / 256, 256, 0, s>>>(W.dH1, int(n), L.h, g + L.b1);
+    k_colsum<<<(L.h + 63) / 64, 1024, 0, s>>>(W.dH1, int(n), L.h, g + L.b1);
 }
 
 }  // namespace h2
