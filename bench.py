@@ -50,6 +50,30 @@ def near_kernel_bytes(d) -> float:
     return 16.0 * (d.near.size + d.basis.size) + 16.0 * 3 * n3
 
 
+def near_sym_bytes(d):
+    """Algorithmic bytes of the symmetric near-field launch (k_near_sym) and of its
+    finishing launch (k_near_sym_finish), FP64, 3 columns.
+
+    k_near_sym streams each unordered leaf pair once (16 bytes per entry of the
+    t <= s blocks: (sum over all ordered blocks + sum of the diagonal blocks) / 2
+    entries), reads U and writes each leaf's own rows (16 bytes x 3 per voxel
+    each) and writes one 3-column partial per pair for the leaf that does not
+    stream it.  k_near_sym_finish reads the rows and partials back, the leaf bases,
+    x, and writes y.
+    """
+    import numpy as np
+    size = (d.end - d.begin).astype(np.int64)
+    leaf = d.nchild == 0
+    diag = float((size[leaf] ** 2).sum())
+    owned = (float(d.near.size) + diag) / 2.0
+    off = d.near_t != d.near_s
+    other = 0.5 * float((size[d.near_t[off]]).sum())          # sum over unordered pairs of (n_t + n_s) / 2
+    n3 = 3 * int(d.n_vox)
+    main = 16.0 * owned + 16.0 * 3 * other + 2 * 16.0 * n3
+    finish = 16.0 * 3 * other + 16.0 * d.basis.size + 3 * 16.0 * n3
+    return main, finish
+
+
 def measured_traffic(workload: str, kernel: str = "k_near_epilogue"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel
     source is unchanged since the counters were taken (else None)."""
@@ -75,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solves")
+    ap.add_argument("--near", choices=("auto", "full"), default="auto",
+                    help="near-field mode of the FP64 product: symmetric when available (auto), or every block")
     ap.add_argument("--cache", default=None,
                     help="directory holding a saved representation of the workload (built and saved if absent)")
     ap.add_argument("--batched", action="store_true",
@@ -151,6 +177,8 @@ def main():
     torch.cuda.set_device(dev)
     t0 = time.time()
     H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0")
+    if args.near == "full":
+        H.near_mode(False)
     upload_s = time.time() - t0
     st = H.stats()
     log(f"[bench] upload {upload_s:.1f}s, device buffer {st['dev_bytes']/1e9:.2f} GB")
@@ -177,16 +205,24 @@ def main():
     fam_n = np.frombuffer(bytes(buf)[64:], np.int64).copy()
     H.lib.h2_profile_enable(H.handle, 0)
     ms_per = total_ms / args.steps
-    names = ["prologue", "leaf_forward", "upward", "coupling", "downward", "near_epilogue"]
-    fam = {names[i]: round(float(fam_ms[i] / max(fam_n[i], 1)), 4) for i in range(6)}
+    sym = H.near_mode()[0]
+    names = ["prologue", "leaf_forward", "upward", "coupling", "downward",
+             "near_sym" if sym else "near_epilogue", "near_sym_finish"]
+    fam = {names[i]: round(float(fam_ms[i] / max(fam_n[i], 1)), 4) for i in range(7) if fam_n[i] > 0}
     log(f"[bench] {ms_per:.3f} ms per product; per family (ms): {fam}")
 
     near_ms = fam_ms[5] / max(fam_n[5], 1)
-    nb = near_kernel_bytes(d)
+    if sym:
+        nb, nb_finish = near_sym_bytes(d)
+        product_bytes = st["bytes_fp64"] - 16.0 * d.near.size + nb - 2 * 16.0 * 3 * g.n_vox + nb_finish
+    else:
+        nb = near_kernel_bytes(d)
+        product_bytes = st["bytes_fp64"]
+    near_kernel = "k_near_sym" if sym else "k_near_epilogue"
     achieved = nb / (near_ms * 1e-3) / 1e9
     coup_ms = fam_ms[3] / max(fam_n[3], 1)
     coup_bytes = 16.0 * d.coupling.size + 4.0 * sum(int(r) for r in d.rank[d.far_s])
-    whole_gbs = st["bytes_fp64"] / (ms_per * 1e-3) / 1e9
+    whole_gbs = product_bytes / (ms_per * 1e-3) / 1e9
 
     result_gpu = y.cpu().numpy()
     extra = {}
@@ -246,10 +282,11 @@ def main():
                                f"eps_r {eps_r}, seed {seed}, leaf 64, eta 1, eps {eps}",
                    "N": 3 * g.n_vox, "n_rhs": 1, "precision": "fp64"},
         "hbm_gbs_whole_product": round(whole_gbs, 2),
-        "algorithmic_bytes_per_product": st["bytes_fp64"],
-        "roofline": {"bound": "hbm", "kernel": "k_near_epilogue", "achieved": round(achieved, 2),
+        "algorithmic_bytes_per_product": product_bytes,
+        "near_mode": "symmetric" if sym else "full",
+        "roofline": {"bound": "hbm", "kernel": near_kernel, "achieved": round(achieved, 2),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(args.workload), "bytes_per_launch": nb,
+                     "traffic": measured_traffic(args.workload, near_kernel), "bytes_per_launch": nb,
                      "avg_ms": round(float(near_ms), 4)},
         "coupling_kernel": {"avg_ms": round(float(coup_ms), 4),
                             "achieved_gbs": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2) if coup_ms > 0 else None},

@@ -310,7 +310,10 @@ enum {
     H2_K_UPWARD = 2,        /* X_p = sum T_c^T X_c */
     H2_K_COUPLING = 3,      /* Y_t = sum S_ts X_s */
     H2_K_DOWNWARD = 4,      /* Y_c += T_c Y_p */
-    H2_K_NEAR = 5,          /* near field + leaf backward + epilogue */
+    H2_K_NEAR = 5,          /* near field + leaf backward + epilogue; in the symmetric
+                               near mode the near field alone (own rows and the partials
+                               of the other leaf of each streamed pair) */
+    H2_K_NEAR_FINISH = 6,   /* symmetric near mode: partials + leaf backward + epilogue */
     H2_K_FAMILIES = 8
 };
 
@@ -318,6 +321,22 @@ typedef struct {
     double ms[H2_K_FAMILIES];        /* summed device time per family */
     int64_t launches[H2_K_FAMILIES]; /* launches per family */
 } h2_kernel_times;
+
+/* Near-field mode of the FP64 and FP32 single-vector products.  The scalar
+ * kernel matrix is symmetric (Sec. II: G depends on |r - r'| only), and when the
+ * description's near blocks satisfy G_st = G_ts^T bit for bit (checked at
+ * build), the library can stream each unordered leaf pair once: one leaf of the
+ * pair adds G_ts u_s to its rows and writes G_ts^T u_t for the other, which adds
+ * it when it finishes.  This halves the near-field stream; results agree with
+ * the full mode to rounding (the sums are taken in another order).
+ *   set: -1 query only, 0 stream every ordered block, 1 the symmetric mode
+ *   *mode: the mode in use after the call; *available: 1 if the symmetric mode
+ *   can be used (either output may be NULL).
+ * Handles start in the symmetric mode when it is available.  The multi-RHS
+ * products (n_rhs > 1) and the BF16x3 tier stream every block in both modes.
+ * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 when the
+ * mode is not available. */
+h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);
 
 /* Diagnostics: with enable = 1, later products on h bracket every kernel
  * family with HIP events on the product's stream; h2_profile_read waits for

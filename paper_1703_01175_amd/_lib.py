@@ -122,6 +122,8 @@ def load() -> C.CDLL:
     lib.h2_profile_enable.argtypes = [vp, C.c_int]
     lib.h2_profile_read.restype = C.c_int
     lib.h2_profile_read.argtypes = [vp, vp]
+    lib.h2_near_mode.restype = C.c_int
+    lib.h2_near_mode.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     pd = C.POINTER(MlpDims)
     for name, args in [
         ("h2_mlp_sizes", [pd, C.c_int64, C.POINTER(sz), C.POINTER(sz)]),

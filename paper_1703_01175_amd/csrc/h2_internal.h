@@ -79,6 +79,20 @@ struct DevH2 {
     const int* up_list = nullptr;       // parents with rank > 0, grouped by level (deepest first)
     const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)
 
+    // symmetric near field (each unordered leaf pair streamed once; see the plan)
+    bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
+    bool near_sym = false;              // products use it (selectable while near_sym_ok)
+    const int* sym_leaf = nullptr;      // [n_leaves] leaves in launch order (most owned blocks first)
+    const int* sym_ptr = nullptr;       // [n_leaves + 1] into the owned block list (diagonal first)
+    const int* sym_sbeg = nullptr;      // per owned block: tree position of the other leaf
+    const int* sym_ssize = nullptr;     // per owned block: its size
+    const int* sym_pslot = nullptr;     // per owned block: partial slot of G^T u_t (-1: diagonal)
+    const int* sym_in_ptr = nullptr;    // [n_leaves + 1] into sym_in_slot, by launch slot
+    const int* sym_in_slot = nullptr;   // partial slots that land in each leaf
+    const int64_t* sym_off = nullptr;   // per owned block: complex offset of G_(owner, other)
+    void* sym_part = nullptr;           // [pairs][kMaxLeaf][3] partials (vector type)
+    void* sym_rows = nullptr;           // [n_vox][3] tree order: each leaf's own rows
+
     LeafInfo leaves;
 
     TierData tier[3];

@@ -337,6 +337,202 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
     }
 }
 
+// ---------------------------------------------------------------- symmetric near field
+// Sum over the 16 lanes of each DPP row (rotations by 8, 4, 2, 1): every lane of
+// the row ends with the row's sum.  All 64 lanes must be active.
+template <int R> __device__ __forceinline__ double ror_row(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x120 + R, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x120 + R, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int R> __device__ __forceinline__ float ror_row(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + R, 0xf, 0xf, false));
+}
+template <typename T> __device__ __forceinline__ T rowsum16(T v) {
+    v += ror_row<8>(v);
+    v += ror_row<4>(v);
+    v += ror_row<2>(v);
+    v += ror_row<1>(v);
+    return v;
+}
+
+// One group per leaf t (launch slot); its four waves take t's owned blocks in
+// turn (the diagonal block, then the pairs t streams for both leaves).  Lane
+// (cg = lane / 16, rg = lane % 16) holds rows rg + 16 q (q < 4) of t and, in
+// panel k of four columns, column j = 4 k + cg of the block:
+//   own rows      acc[q] += G(rg + 16 q, j) u_s(j)           (summed over cg at the end)
+//   other leaf    part(j) = sum_i G(i, j) u_t(i)             (DPP row sum over rg)
+// Own rows go to rows (tree order), the other leaf's to its partial slot.
+template <typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_near_sym(const int* __restrict__ sym_leaf, const int* __restrict__ sym_ptr,
+                                                  const int* __restrict__ sym_sbeg, const int* __restrict__ sym_ssize,
+                                                  const int64_t* __restrict__ sym_off, const int* __restrict__ sym_pslot,
+                                                  const TB* __restrict__ near, const int* __restrict__ cl_begin,
+                                                  const int* __restrict__ cl_size, const TV* __restrict__ U,
+                                                  TV* __restrict__ rows, TV* __restrict__ part) {
+    __shared__ TV red[4][kMaxLeaf][3];
+    __shared__ TV ut[kMaxLeaf][3];               // u_t, read by every column product
+    const int slot = blockIdx.x;
+    const int t = sym_leaf[slot];
+    const int n = cl_size[t], tb = cl_begin[t];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rg = lane & 15, cg = lane >> 4;
+    if (threadIdx.x < kMaxLeaf * 3)
+        ut[threadIdx.x / 3][threadIdx.x % 3] =
+            threadIdx.x < n * 3 ? U[(int64_t)tb * kNcomp + threadIdx.x] : czero<TV>();
+    TV acc[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[q][c] = czero<TV>();
+    __syncthreads();
+    const int e = sym_ptr[slot + 1];
+    for (int blk = sym_ptr[slot] + w; blk < e; blk += 4) {
+        const int sb = sym_sbeg[blk];
+        const int ns = sym_ssize[blk];
+        const int ps = sym_pslot[blk];
+        const TB* G = near + sym_off[blk];
+        const TV* us = U + (int64_t)sb * kNcomp;
+        // panel k holds columns 4k .. 4k + 3.  Loads have no branches or selects:
+        // entries outside the block read the block's first entry (finite), which
+        // meets a zero (u_t beyond n in LDS, u_s beyond ns masked where it is used)
+        // or lands in a row or column that is not stored.  Column 4k + cg of the
+        // other leaf is kept by lane rg = k and stored once per block.
+        TV keep[3];
+        auto load_panel = [&](int k, TB* dst, TV* du) {
+            const int j = 4 * k + cg;
+            const bool jv = j < ns;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = rg + 16 * q;
+                dst[q] = ldnt(G + ((jv && i < n) ? (int64_t)j * n + i : 0));
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) du[c] = us[jv ? j * 3 + c : c];
+        };
+        auto panel = [&](int k, const TB* g, const TV* u) {
+            const bool jv = 4 * k + cg < ns;
+            TV um[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                um[c].x = jv ? u[c].x : 0;
+                um[c].y = jv ? u[c].y : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cfma(acc[q][c], g[q], um[c]);
+            if (ps >= 0) {   // wave-uniform: off-diagonal pair, the other leaf's rows
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    TV p = czero<TV>();
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cfma(p, g[q], ut[rg + 16 * q][c]);
+                    p.x = rowsum16(p.x);
+                    p.y = rowsum16(p.y);
+                    keep[c].x = rg == k ? p.x : keep[c].x;
+                    keep[c].y = rg == k ? p.y : keep[c].y;
+                }
+            }
+        };
+#pragma unroll
+        for (int c = 0; c < 3; ++c) keep[c] = czero<TV>();
+        // one panel at a time: latency is hidden by the other waves of the SIMD
+        const int npan = (ns + 3) >> 2;
+        for (int k = 0; k < npan; ++k) {
+            TB g[4];
+            TV u[3];
+            load_panel(k, g, u);
+            panel(k, g, u);
+        }
+        const int jk = 4 * rg + cg;
+        if (ps >= 0 && jk < ns) {
+            TV* pj = part + ((int64_t)ps * kMaxLeaf + jk) * kNcomp;
+            pj[0] = keep[0];
+            pj[1] = keep[1];
+            pj[2] = keep[2];
+        }
+    }
+    // own rows: sum over the four column groups of the wave, then over the waves
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[q][c].x += __shfl_xor(acc[q][c].x, 16);
+            acc[q][c].y += __shfl_xor(acc[q][c].y, 16);
+            acc[q][c].x += __shfl_xor(acc[q][c].x, 32);
+            acc[q][c].y += __shfl_xor(acc[q][c].y, 32);
+        }
+    if (cg == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = rg + 16 * q;
+            if (i < n)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red[w][i][c] = acc[q][c];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < n) {
+        const int i = threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            TV s = cadd(cadd(red[0][i][c], red[1][i][c]), cadd(red[2][i][c], red[3][i][c]));
+            rows[(int64_t)(tb + i) * kNcomp + c] = s;
+        }
+    }
+}
+
+// One wave per leaf: own rows + the partials other leaves wrote for it (fixed
+// order) + V_t Y_t, then the epilogue, as k_near_epilogue.
+template <typename TB, typename TV>
+__global__ __launch_bounds__(64) void k_near_sym_finish(
+    const int* __restrict__ sym_leaf, const int* __restrict__ in_ptr, const int* __restrict__ in_slot,
+    const TV* __restrict__ rows, const TV* __restrict__ part, const int* __restrict__ cl_rank,
+    const int* __restrict__ cl_coef, const int* __restrict__ cl_begin, const int* __restrict__ cl_size,
+    const int64_t* __restrict__ cl_basis_off, const TB* __restrict__ basis, const TV* __restrict__ Yh,
+    const int* __restrict__ perm, const TV* __restrict__ x, TV* __restrict__ y, int op, typename Real<TV>::T alpha) {
+    const int slot = blockIdx.x;
+    const int t = sym_leaf[slot];
+    const int n = cl_size[t];
+    const int lane = threadIdx.x;
+    if (lane >= n) return;
+    const int64_t r = (int64_t)(cl_begin[t] + lane) * kNcomp;
+    TV s0 = rows[r], s1 = rows[r + 1], s2 = rows[r + 2];
+    const int e = in_ptr[slot + 1];
+#pragma unroll 4
+    for (int k = in_ptr[slot]; k < e; ++k) {
+        const TV* p = part + ((int64_t)in_slot[k] * kMaxLeaf + lane) * kNcomp;
+        s0 = cadd(s0, p[0]);
+        s1 = cadd(s1, p[1]);
+        s2 = cadd(s2, p[2]);
+    }
+    const int k = cl_rank[t];
+    if (k > 0) {   // backward transformation at the leaf: y_t += V_t Y_t
+        const TB* V = basis + cl_basis_off[t];
+        const TV* yt = Yh + (int64_t)cl_coef[t] * kNcomp;
+        for (int a = 0; a < k; ++a) {
+            TB v = V[(int64_t)a * n + lane];
+            cfma(s0, v, yt[a * 3 + 0]);
+            cfma(s1, v, yt[a * 3 + 1]);
+            cfma(s2, v, yt[a * 3 + 2]);
+        }
+    }
+    const int vox = perm[cl_begin[t] + lane];
+    TV* yo = y + (int64_t)vox * kNcomp;
+    if (op == 1) {
+        const TV* xi = x + (int64_t)vox * kNcomp;
+        TV o;
+        o.x = xi[0].x + alpha * s0.x; o.y = xi[0].y + alpha * s0.y; yo[0] = o;
+        o.x = xi[1].x + alpha * s1.x; o.y = xi[1].y + alpha * s1.y; yo[1] = o;
+        o.x = xi[2].x + alpha * s2.x; o.y = xi[2].y + alpha * s2.y; yo[2] = o;
+    } else {
+        yo[0] = s0; yo[1] = s1; yo[2] = s2;
+    }
+}
+
 // ---------------------------------------------------------------- launcher
 template <typename TB, typename TV>
 static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, const TierData& td, const TV* x,
@@ -383,10 +579,24 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             end(4);
         }
         begin(5);
-        k_near_epilogue<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off,
-                                                           near, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
-                                                           d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
-        end(5);
+        if (d.near_sym) {
+            k_near_sym<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.sym_leaf, d.sym_ptr, d.sym_sbeg, d.sym_ssize, d.sym_off,
+                                                          d.sym_pslot, near, d.cl_begin, d.cl_size, U, (TV*)d.sym_rows,
+                                                          (TV*)d.sym_part);
+            end(5);
+            begin(6);
+            k_near_sym_finish<TB, TV><<<d.n_leaves, 64, 0, s>>>(d.sym_leaf, d.sym_in_ptr, d.sym_in_slot,
+                                                                (const TV*)d.sym_rows, (const TV*)d.sym_part, d.cl_rank,
+                                                                d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis,
+                                                                Yh, d.perm, xr, yr, op, alpha);
+            end(6);
+        } else {
+            k_near_epilogue<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize,
+                                                               d.near_off, near, d.cl_rank, d.cl_coef, d.cl_begin,
+                                                               d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr,
+                                                               op, alpha);
+            end(5);
+        }
     }
     return hipGetLastError();
 }

@@ -2,6 +2,9 @@
 // description, packing into the caller's device buffer, handles, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <thread>
+
 #include <algorithm>
 #include <cstdarg>
 #include <mutex>
@@ -51,6 +54,12 @@ struct Plan {
     std::vector<int64_t> cl_toff, cl_boff;
     std::vector<int> leaf_id, near_ptr, near_sbeg, near_ssize;
     std::vector<int64_t> near_off;
+    // symmetric near field: each unordered leaf pair once (empty when G_st != G_ts^T somewhere)
+    bool sym = false;
+    int64_t sym_pairs = 0;
+    std::vector<int> sym_leaf, sym_ptr, sym_sbeg, sym_ssize, sym_pslot, sym_in_ptr, sym_in_slot;
+    std::vector<int64_t> sym_off;
+    size_t o_sym[7] = {0, 0, 0, 0, 0, 0, 0}, o_symoff = 0, o_sympart = 0, o_symrows = 0;
     std::vector<int> row_cl, row_ncols, row_colptr, colsrc;
     std::vector<int64_t> row_off;
     std::vector<int> up_list, down_list;
@@ -183,6 +192,96 @@ h2_status validate(const h2_host_desc* d) {
     return H2_OK;
 }
 
+// Symmetric near field.  G is symmetric (G_ij = G_ji), so when the description's
+// blocks satisfy G_st = G_ts^T bit for bit, each unordered leaf pair {t, s} is
+// streamed once by one of its two leaves (the owner, chosen to balance the blocks
+// per leaf): the owner adds G_ts u_s to its own rows and writes G_ts^T u_t for
+// the other leaf into a partial slot, which that leaf adds when it finishes.
+// Diagonal blocks stay with their leaf.  Any asymmetric or unmatched pair leaves
+// the plan without this mode.
+static void plan_symmetric_near(const h2_host_desc* d, const std::vector<int64_t>& nfirst,
+                                const std::vector<int64_t>& ncount, Plan& P) {
+    const int nc = d->n_clusters;
+    auto size = [&](int c) { return int(d->end[c] - d->begin[c]); };
+    // mirror of every off-diagonal pair (t, s), t < s
+    struct Pair { int t, s; int64_t it, is; };     // near index of (t, s) and of (s, t)
+    std::vector<Pair> pairs;
+    for (int t = 0; t < nc; ++t) {
+        if (d->nchild[t] != 0) continue;
+        for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i) {
+            const int s = d->near_s[i];
+            if (s <= t) continue;
+            int64_t j = -1;
+            for (int64_t k = nfirst[s]; k < nfirst[s] + ncount[s]; ++k)
+                if (d->near_s[k] == t) { j = k; break; }
+            if (j < 0) return;
+            pairs.push_back({t, s, i, j});
+        }
+    }
+    // bitwise check G_st = G_ts^T, pairs split over host threads
+    std::atomic<bool> same(true);
+    auto check = [&](size_t a, size_t b) {
+        for (size_t q = a; q < b && same.load(std::memory_order_relaxed); ++q) {
+            const Pair& pr = pairs[q];
+            const int nt = size(pr.t), ns = size(pr.s);
+            const double* gts = d->near_blocks + 2 * d->near_off[pr.it];   // nt x ns, column major
+            const double* gst = d->near_blocks + 2 * d->near_off[pr.is];   // ns x nt, column major
+            for (int b2 = 0; b2 < ns; ++b2)
+                for (int a2 = 0; a2 < nt; ++a2)
+                    if (std::memcmp(gts + 2 * (int64_t(b2) * nt + a2), gst + 2 * (int64_t(a2) * ns + b2), 16) != 0) {
+                        same.store(false);
+                        return;
+                    }
+        }
+    };
+    const size_t nth = std::max<size_t>(1, std::min<size_t>(8, pairs.size() / 4096 + 1));
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < nth; ++k)
+        th.emplace_back(check, pairs.size() * k / nth, pairs.size() * (k + 1) / nth);
+    for (auto& x : th) x.join();
+    if (!same.load()) return;
+    // owners: each pair goes to the endpoint with fewer owned blocks so far
+    std::vector<int> owned(nc, 0);
+    std::vector<std::vector<std::pair<int64_t, int>>> own(nc);   // (near index of (owner, other), slot)
+    std::vector<std::vector<int>> inc(nc);                        // slots landing in a leaf
+    for (size_t q = 0; q < pairs.size(); ++q) {
+        const Pair& pr = pairs[q];
+        const bool to_t = owned[pr.t] <= owned[pr.s];
+        const int ow = to_t ? pr.t : pr.s, ot = to_t ? pr.s : pr.t;
+        owned[ow]++;
+        own[ow].push_back({to_t ? pr.it : pr.is, int(q)});
+        inc[ot].push_back(int(q));
+    }
+    std::vector<int> leaves;
+    for (int c = 0; c < nc; ++c)
+        if (d->nchild[c] == 0) leaves.push_back(c);
+    std::stable_sort(leaves.begin(), leaves.end(), [&](int a, int b) { return owned[a] > owned[b]; });
+    P.sym_leaf = leaves;
+    P.sym_ptr.assign(1, 0);
+    P.sym_in_ptr.assign(1, 0);
+    for (int t : leaves) {
+        for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i)   // the diagonal block first
+            if (d->near_s[i] == t) {
+                P.sym_sbeg.push_back(int(d->begin[t]));
+                P.sym_ssize.push_back(size(t));
+                P.sym_off.push_back(d->near_off[i]);
+                P.sym_pslot.push_back(-1);
+            }
+        for (auto& o : own[t]) {
+            const int other = d->near_s[o.first];
+            P.sym_sbeg.push_back(int(d->begin[other]));
+            P.sym_ssize.push_back(size(other));
+            P.sym_off.push_back(d->near_off[o.first]);
+            P.sym_pslot.push_back(o.second);
+        }
+        P.sym_ptr.push_back(int(P.sym_off.size()));
+        for (int q : inc[t]) P.sym_in_slot.push_back(q);
+        P.sym_in_ptr.push_back(int(P.sym_in_slot.size()));
+    }
+    P.sym_pairs = int64_t(pairs.size());
+    P.sym = true;
+}
+
 h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     h2_status st = validate(d);
     if (st != H2_OK) return st;
@@ -243,6 +342,8 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         if (P.near_off.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many near blocks");
         P.near_ptr.push_back(int(P.near_off.size()));
     }
+
+    plan_symmetric_near(d, nfirst, ncount, P);
 
     // leaves in cluster order with their diagonal near block (per-leaf preconditioners)
     for (int c = 0; c < nc; ++c) {
@@ -328,6 +429,14 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     P.o_ldiag = L.add(i64s(P.lc_diag.size()));
     P.o_linv = L.add(i64s(P.lc_inv.size()));
     P.o_down = L.add(ints(P.down_list.size()));
+    if (P.sym) {
+        const std::vector<int>* sv[7] = {&P.sym_leaf, &P.sym_ptr, &P.sym_sbeg, &P.sym_ssize, &P.sym_pslot,
+                                         &P.sym_in_ptr, &P.sym_in_slot};
+        for (int q = 0; q < 7; ++q) P.o_sym[q] = L.add(ints(sv[q]->size()));
+        P.o_symoff = L.add(i64s(P.sym_off.size()));
+        P.o_sympart = L.add(size_t(std::max<int64_t>(P.sym_pairs, 1)) * kMaxLeaf * kNcomp * 16);
+        P.o_symrows = L.add(size_t(n) * kNcomp * 16);
+    }
     const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
     for (int tier = 0; tier < 3; ++tier)
         for (int q = 0; q < 4; ++q) P.o_data[tier][q] = 0;
@@ -428,6 +537,12 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     errs.push_back(put(P.o_ldiag, P.lc_diag.data(), P.lc_diag.size() * 8));
     errs.push_back(put(P.o_linv, P.lc_inv.data(), P.lc_inv.size() * 8));
     errs.push_back(put(P.o_down, P.down_list.data(), P.down_list.size() * 4));
+    if (P.sym) {
+        const std::vector<int>* sv[7] = {&P.sym_leaf, &P.sym_ptr, &P.sym_sbeg, &P.sym_ssize, &P.sym_pslot,
+                                         &P.sym_in_ptr, &P.sym_in_slot};
+        for (int q = 0; q < 7; ++q) errs.push_back(put(P.o_sym[q], sv[q]->data(), sv[q]->size() * 4));
+        errs.push_back(put(P.o_symoff, P.sym_off.data(), P.sym_off.size() * 8));
+    }
     const double* src[4] = {d->near_blocks, d->coupling, d->basis, d->transfer};
     const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
     for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_data[0][q], src[q], size_t(lens[q]) * 16));
@@ -485,6 +600,20 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.leaves.inv_elems = P.lc_inv_elems;
     D.leaves.max_leaf = P.lc_max;
     D.down_list = (const int*)(base + P.o_down);
+    if (P.sym) {
+        D.near_sym_ok = true;
+        D.near_sym = true;
+        D.sym_leaf = (const int*)(base + P.o_sym[0]);
+        D.sym_ptr = (const int*)(base + P.o_sym[1]);
+        D.sym_sbeg = (const int*)(base + P.o_sym[2]);
+        D.sym_ssize = (const int*)(base + P.o_sym[3]);
+        D.sym_pslot = (const int*)(base + P.o_sym[4]);
+        D.sym_in_ptr = (const int*)(base + P.o_sym[5]);
+        D.sym_in_slot = (const int*)(base + P.o_sym[6]);
+        D.sym_off = (const int64_t*)(base + P.o_symoff);
+        D.sym_part = base + P.o_sympart;
+        D.sym_rows = base + P.o_symrows;
+    }
     for (int tier = 0; tier < 3; ++tier) {
         D.has_tier[tier] = (P.tiers >> tier) & 1;
         if (!D.has_tier[tier] || tier == 2) continue;
@@ -598,6 +727,17 @@ h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* 
                        : launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld,
                                        reinterpret_cast<hipStream_t>(stream), h->prof);
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "matvec launch failed: %s", hipGetErrorString(e));
+    return H2_OK;
+}
+
+h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (set < -1 || set > 1) return fail(H2_ERR_INVALID_ARG, "near mode must be -1, 0 or 1");
+    if (set == 1 && !h->dev.near_sym_ok)
+        return fail(H2_ERR_INVALID_ARG, "the near blocks are not symmetric: no symmetric near mode");
+    if (set >= 0) h->dev.near_sym = set == 1;
+    if (mode) *mode = h->dev.near_sym ? 1 : 0;
+    if (available) *available = h->dev.near_sym_ok ? 1 : 0;
     return H2_OK;
 }
 

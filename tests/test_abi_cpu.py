@@ -51,6 +51,21 @@ def test_plan_ok(desc):
     assert st2 == 0 and n2 > n
 
 
+def test_plan_reserves_partials_only_for_symmetric_near_blocks(desc):
+    """The plan checks G_st = G_ts^T bit for bit on the host: the symmetric near
+    mode's partial slots (one 64 x 3 complex slot per unordered leaf pair) are
+    reserved for the generated description and not once one entry is changed."""
+    st, n = _plan(desc)
+    i = int(np.nonzero(desc.near_t != desc.near_s)[0][0])
+    e = copy.copy(desc)
+    e.near = desc.near.copy()
+    e.near[desc.near_off[i] + 1] *= 1.5
+    st2, n2 = _plan(e)
+    pairs = int((desc.near_t != desc.near_s).sum()) // 2
+    assert st == 0 and st2 == 0
+    assert n - n2 >= pairs * 64 * 3 * 16 + 16 * desc.n_vox * 3
+
+
 def _corrupt(desc, field, fn):
     e = copy.copy(desc)
     setattr(e, field, fn(np.array(getattr(desc, field))))

@@ -125,3 +125,46 @@ def test_profile_counts_kernel_families(torch):
     launches = np.frombuffer(bytes(buf)[64:], np.int64)
     assert launches[5] == 3 and launches[0] == 3 and ms[5] > 0
     assert lib.h2_profile_enable(H.handle, 0) == 0
+
+
+@pytest.mark.parametrize("name", ["cube12", "rod", "slab", "cube13", "box9"])
+def test_symmetric_near_mode_matches_full_mode_and_oracle(torch, name):
+    """The near blocks of G are transposes of each other bit for bit, so the
+    symmetric near mode is available; both modes match the oracle, in FP64 and
+    FP32, and agree with each other to rounding."""
+    print(f"[gpu] near modes {name}", flush=True)
+    g, d, H = operator(name)
+    assert H.near_mode() == (True, True)
+    x = h2gen.random_vector(3 * g.n_vox, 23)
+    xs = torch.from_numpy(x).cuda()
+    ys = H.matvec(xs).cpu().numpy()
+    yf32s = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
+    assert H.near_mode(False) == (False, True)
+    yf = H.matvec(xs).cpu().numpy()
+    yf32f = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
+    H.near_mode(True)
+    yo = om.h2_matvec(d, x)
+    assert _rel(ys, yo) <= 1e-12 and _rel(yf, yo) <= 1e-12
+    assert _rel(ys, yf) <= 1e-13
+    assert _rel(yf32s, yo) <= 1e-5 and _rel(yf32f, yo) <= 1e-5
+
+
+def test_asymmetric_near_blocks_use_the_full_mode(torch):
+    """One off-diagonal near entry changed: the symmetric mode is not offered and
+    the product follows the changed description."""
+    import dataclasses
+    from paper_1703_01175_amd import H2Operator
+    from paper_1703_01175_amd._lib import H2Error
+    g, d = built("cube12")
+    i = int(np.nonzero(d.near_t != d.near_s)[0][0])
+    near = d.near.copy()
+    near[d.near_off[i] + 1] *= 1.5
+    d2 = dataclasses.replace(d, near=near)
+    H = H2Operator(d2, tiers=("fp64",))
+    assert H.near_mode() == (False, False)
+    with pytest.raises(H2Error):
+        H.near_mode(True)
+    x = h2gen.random_vector(3 * g.n_vox, 29)
+    y = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, om.h2_matvec(d2, x)) <= 1e-12
+    H.close()
