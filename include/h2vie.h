@@ -119,7 +119,17 @@ typedef struct {
     int32_t max_rhs;        /* most right-hand sides one call carries (>= 1) */
     int32_t tiers;          /* bit mask (1 << h2_precision) of storage tiers to hold;
                                FP64 is always held */
+    int32_t flags;          /* H2_BUILD_* bits (0: defaults) */
+    int32_t pad;
 } h2_build_opts;
+
+/* Near blocks that are identical bit for bit (same size and entries: on a uniform
+ * voxel grid, every leaf pair of the same shape and relative position, since the
+ * kernel depends on the offset between voxel centres only) are stored once on the
+ * device and read through the caches, when that at least halves the near-block
+ * storage; every block product is still carried out.  This flag keeps one stored
+ * copy per near pair instead. */
+#define H2_BUILD_KEEP_ALL_NEAR 1
 
 /* Size (bytes) of the device buffer h2_build_from_host needs for d and o.
  * Validates d (same checks as the build).  Errors: INVALID_ARG, BAD_DESC. */
@@ -233,6 +243,9 @@ typedef struct {
     int64_t dev_bytes;             /* planned buffer size */
     double bytes_fp64;             /* algorithmic bytes of one FP64 product with 3 columns */
     double flops_fp64;             /* real flops of one product with 3 columns */
+    int64_t near_stored_elems;     /* complex entries of the near blocks held on the device
+                                      (near_elems unless identical blocks are stored once) */
+    int64_t near_unique;           /* distinct near blocks held */
 } h2_stats_t;
 
 h2_status h2_stats(h2_handle h, h2_stats_t* out);
@@ -332,7 +345,10 @@ typedef struct {
  *   set: -1 query only, 0 stream every ordered block, 1 the symmetric mode
  *   *mode: the mode in use after the call; *available: 1 if the symmetric mode
  *   can be used (either output may be NULL).
- * Handles start in the symmetric mode when it is available.  The multi-RHS
+ * Handles start in the symmetric mode when it is available and the near blocks
+ * are streamed from memory; when identical blocks are stored once (see
+ * H2_BUILD_KEEP_ALL_NEAR) they are read from the caches and handles start in the
+ * full mode, which is then the faster one.  The multi-RHS
  * products (n_rhs > 1) and the BF16x3 tier stream every block in both modes.
  * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 when the
  * mode is not available. */

@@ -39,7 +39,7 @@ class HostDesc(C.Structure):
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("max_rhs", C.c_int32), ("tiers", C.c_int32)]
+    _fields_ = [("max_rhs", C.c_int32), ("tiers", C.c_int32), ("flags", C.c_int32), ("pad", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -66,7 +66,8 @@ class Stats(C.Structure):
                 ("n_near", C.c_int64), ("depth", C.c_int64), ("near_elems", C.c_int64),
                 ("coupling_elems", C.c_int64), ("basis_elems", C.c_int64), ("transfer_elems", C.c_int64),
                 ("coef_rows", C.c_int64), ("max_rank", C.c_int32), ("min_leaf_rank", C.c_int32),
-                ("dev_bytes", C.c_int64), ("bytes_fp64", C.c_double), ("flops_fp64", C.c_double)]
+                ("dev_bytes", C.c_int64), ("bytes_fp64", C.c_double), ("flops_fp64", C.c_double),
+                ("near_stored_elems", C.c_int64), ("near_unique", C.c_int64)]
 
 
 _LIB = None

@@ -30,7 +30,8 @@ class GmresResult:
 class H2Operator:
     """Device copy of an h2gen.H2Desc; matvec(x) applies Z (or G) on the GPU."""
 
-    def __init__(self, desc, tiers=("fp64",), max_rhs: int = 1, device: str = "cuda", stream=None):
+    def __init__(self, desc, tiers=("fp64",), max_rhs: int = 1, device: str = "cuda", stream=None,
+                 keep_all_near: bool = False):
         import torch
         self.lib = _lib.load()
         self.N = 3 * int(desc.n_vox)
@@ -40,7 +41,7 @@ class H2Operator:
         for t in tiers:
             mask |= _TIER_BITS[t]
         self.tiers = tuple(tiers)
-        opts = _lib.BuildOpts(max_rhs=int(max_rhs), tiers=mask)
+        opts = _lib.BuildOpts(max_rhs=int(max_rhs), tiers=mask, flags=1 if keep_all_near else 0)
         nbytes = C.c_size_t(0)
         _lib.check(self.lib.h2_plan_from_host(C.byref(hd), C.byref(opts), C.byref(nbytes)))
         self.device = torch.device(device)

@@ -41,7 +41,8 @@ bool handle_live(h2_handle h);
 h2_status handle_fail(h2_status st, const char* msg);
 
 // Batched BF16x3 tier (h2_batch_api.cpp)
-h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B);
+// near_off: offset of each near pair's block in the stored FP64 near array
+h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, BatchHost& B);
 size_t group_need(const h2_handle* hs, int n);
 size_t group_need_batch(BatchHost* B);
 h2_status group_create(const h2_handle* hs, int n, void* mem, size_t bytes, hipStream_t s, h2_group* out);

@@ -22,7 +22,7 @@ namespace h2 {
 static inline int pad16(int v) { return (v + 15) & ~15; }
 
 // ---------------------------------------------------------------- plan of one representation
-h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B) {
+h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, BatchHost& B) {
     const int nc = d->n_clusters;
     for (int c = 0; c < nc; ++c)
         if (d->rank[c] > 64) return H2_ERR_BAD_DESC;      // row blocks of the block GEMM hold <= 64 rows
@@ -149,6 +149,7 @@ h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B) {
     }
     // near field + leaf backward: y_t = sum_s G_ts U_s + V_t Y_t
     {
+        std::map<std::pair<int64_t, std::pair<int, int>>, int64_t> packed_near;
         std::vector<int64_t> nfirst(nc, -1), ncount(nc, 0);
         for (int64_t i = 0; i < d->n_near; ++i) {
             const int t = d->near_t[i];
@@ -164,7 +165,11 @@ h2_status plan_batch(const h2_host_desc* d, int max_rhs, BatchHost& B) {
             RelOwner o{2, urow[t], pad16(n), int(B.near.terms.size()), 0, 0};
             for (int64_t i = nfirst[t]; nfirst[t] >= 0 && i < nfirst[t] + ncount[t]; ++i) {
                 const int s = d->near_s[i];
-                const int64_t a = add_job(0, d->near_off[i], n, size(s), n, 0);
+                // near blocks stored once (identical blocks) are packed once too
+                auto key = std::make_pair(near_off[i], std::make_pair(n, size(s)));
+                auto hit = packed_near.find(key);
+                const int64_t a = hit != packed_near.end() ? hit->second : add_job(0, near_off[i], n, size(s), n, 0);
+                packed_near.emplace(key, a);
                 B.near.terms.push_back({a, 0, urow[s], pad16(size(s))});
                 o.nt++;
             }

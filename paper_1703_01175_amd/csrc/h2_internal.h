@@ -79,6 +79,7 @@ struct DevH2 {
     const int* up_list = nullptr;       // parents with rank > 0, grouped by level (deepest first)
     const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)
 
+    bool near_cached = false;           // identical near blocks stored once: read them through the caches
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
     bool near_sym = false;              // products use it (selectable while near_sym_ok)

@@ -41,6 +41,13 @@ __device__ __forceinline__ float2 ldnt(const float2* p) {
     return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 
+// Near-block loads: streaming (nontemporal) when every block is read once per
+// product, plain cached loads when identical blocks are stored once and reread.
+template <bool NT, typename T> __device__ __forceinline__ T ldblk(const T* p) {
+    if constexpr (NT) return ldnt(p);
+    else return *p;
+}
+
 // Broadcast lane J of each 16-lane row to the whole row (DPP row_newbcast).
 template <int J> __device__ __forceinline__ double bcast_row(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(64) void k_transfer_down(const int* __restrict__ li
 // ---------------------------------------------------------------- near field + leaf backward + epilogue
 // One 256-thread group per leaf t; wave w streams near blocks w, w+4, ...;
 // lane i owns row i of every block (column-major blocks: coalesced columns).
-template <typename TB, typename TV>
+template <typename TB, typename TV, bool NT>
 __global__ __launch_bounds__(256) void k_near_epilogue(
     const int* __restrict__ leaf_id, const int* __restrict__ near_ptr, const int* __restrict__ near_sbeg,
     const int* __restrict__ near_ssize, const int64_t* __restrict__ near_off, const TB* __restrict__ near,
@@ -299,7 +306,7 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
         if (lane < n) {
 #pragma unroll 16
             for (int j = 0; j < ns; ++j) {
-                TB gv = ldnt(Gb + (int64_t)j * n);
+                TB gv = ldblk<NT>(Gb + (int64_t)j * n);
                 cfma(acc0, gv, us[j * 3 + 0]);
                 cfma(acc1, gv, us[j * 3 + 1]);
                 cfma(acc2, gv, us[j * 3 + 2]);
@@ -364,7 +371,7 @@ template <typename T> __device__ __forceinline__ T rowsum16(T v) {
 //   own rows      acc[q] += G(rg + 16 q, j) u_s(j)           (summed over cg at the end)
 //   other leaf    part(j) = sum_i G(i, j) u_t(i)             (DPP row sum over rg)
 // Own rows go to rows (tree order), the other leaf's to its partial slot.
-template <typename TB, typename TV>
+template <typename TB, typename TV, bool NT>
 __global__ __launch_bounds__(256) void k_near_sym(const int* __restrict__ sym_leaf, const int* __restrict__ sym_ptr,
                                                   const int* __restrict__ sym_sbeg, const int* __restrict__ sym_ssize,
                                                   const int64_t* __restrict__ sym_off, const int* __restrict__ sym_pslot,
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(256) void k_near_sym(const int* __restrict__ sym_le
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = rg + 16 * q;
-                dst[q] = ldnt(G + ((jv && i < n) ? (int64_t)j * n + i : 0));
+                dst[q] = ldblk<NT>(G + ((jv && i < n) ? (int64_t)j * n + i : 0));
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) du[c] = us[jv ? j * 3 + c : c];
@@ -580,9 +587,9 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
         }
         begin(5);
         if (d.near_sym) {
-            k_near_sym<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.sym_leaf, d.sym_ptr, d.sym_sbeg, d.sym_ssize, d.sym_off,
-                                                          d.sym_pslot, near, d.cl_begin, d.cl_size, U, (TV*)d.sym_rows,
-                                                          (TV*)d.sym_part);
+            auto kn = d.near_cached ? k_near_sym<TB, TV, false> : k_near_sym<TB, TV, true>;
+            kn<<<d.n_leaves, 256, 0, s>>>(d.sym_leaf, d.sym_ptr, d.sym_sbeg, d.sym_ssize, d.sym_off, d.sym_pslot, near,
+                                          d.cl_begin, d.cl_size, U, (TV*)d.sym_rows, (TV*)d.sym_part);
             end(5);
             begin(6);
             k_near_sym_finish<TB, TV><<<d.n_leaves, 64, 0, s>>>(d.sym_leaf, d.sym_in_ptr, d.sym_in_slot,
@@ -591,10 +598,10 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                 Yh, d.perm, xr, yr, op, alpha);
             end(6);
         } else {
-            k_near_epilogue<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize,
-                                                               d.near_off, near, d.cl_rank, d.cl_coef, d.cl_begin,
-                                                               d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr,
-                                                               op, alpha);
+            auto kn = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
+            kn<<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near,
+                                          d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh,
+                                          d.perm, xr, yr, op, alpha);
             end(5);
         }
     }

@@ -41,6 +41,13 @@ __device__ __forceinline__ float2 mr_ldnt(const float2* p) {
     return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 
+// near-block loads: streaming when each block is read once, cached when identical
+// blocks are stored once and reread
+template <bool NT, typename T> __device__ __forceinline__ T mr_ldblk(const T* p) {
+    if constexpr (NT) return mr_ldnt(p);
+    else return *p;
+}
+
 constexpr int C = kMrCols;
 
 // U[p][3 r + c] = chi[v] x_r[3 v + c] (op Z) or x_r[3 v + c] (op G), v = perm[p]; 0 for r >= nr
@@ -227,7 +234,7 @@ __global__ __launch_bounds__(256) void k_transfer_down_mr(const int* __restrict_
 
 // Near field + leaf backward + epilogue: one group per leaf, wave w streams blocks
 // w, w + 4, ...; lane i owns row i; the source values U_s[j][col] are wave-uniform.
-template <typename TB, typename TV>
+template <typename TB, typename TV, bool NT>
 __global__ __launch_bounds__(256) void k_near_epilogue_mr(
     const int* __restrict__ leaf_id, const int* __restrict__ near_ptr, const int* __restrict__ near_sbeg,
     const int* __restrict__ near_ssize, const int64_t* __restrict__ near_off, const TB* __restrict__ near,
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(256) void k_near_epilogue_mr(
         if (lane < n) {
 #pragma unroll 2
             for (int j = 0; j < ns; ++j) {
-                const TB gv = mr_ldnt(Gb + (int64_t)j * n);
+                const TB gv = mr_ldblk<NT>(Gb + (int64_t)j * n);
 #pragma unroll
                 for (int q = 0; q < C; ++q) mr_fma(acc[q], gv, us[j * C + q]);
             }
@@ -331,10 +338,10 @@ hipError_t mr_tier(const DevH2& d, const LevelLaunch& lv, int op, const TierData
                                                                                 d.cl_rank, d.cl_coef, d.cl_parent,
                                                                                 d.cl_transfer_off, transfer, Yh);
         }
-        k_near_epilogue_mr<TB, TV><<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize,
-                                                              d.near_off, near, d.cl_rank, d.cl_coef, d.cl_begin,
-                                                              d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr,
-                                                              ld, nr, op, alpha);
+        auto kn = d.near_cached ? k_near_epilogue_mr<TB, TV, false> : k_near_epilogue_mr<TB, TV, true>;
+        kn<<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near, d.cl_rank,
+                                      d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr,
+                                      ld, nr, op, alpha);
     }
     return hipGetLastError();
 }

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
 #include <mutex>
 #include <set>
 #include <cmath>
@@ -54,6 +55,12 @@ struct Plan {
     std::vector<int64_t> cl_toff, cl_boff;
     std::vector<int> leaf_id, near_ptr, near_sbeg, near_ssize;
     std::vector<int64_t> near_off;
+    // near blocks as held on the device: offset of each near pair's block in the stored
+    // array, and the source block of every stored one (identical blocks stored once)
+    std::vector<int64_t> near_uoff;
+    std::vector<int64_t> near_src;
+    int64_t near_stored_len = 0;
+    bool near_dedup = false;
     // symmetric near field: each unordered leaf pair once (empty when G_st != G_ts^T somewhere)
     bool sym = false;
     int64_t sym_pairs = 0;
@@ -192,6 +199,85 @@ h2_status validate(const h2_host_desc* d) {
     return H2_OK;
 }
 
+// Identical near blocks stored once.  A 64-bit hash of every block (host threads)
+// proposes the matches, each confirmed bit for bit against the block it would
+// share storage with; a block whose hash matches but whose entries differ keeps
+// its own copy.  Kept only when the stored entries are at most half of them all.
+static void plan_near_dedup(const h2_host_desc* d, bool allow, Plan& P) {
+    const int64_t nn = d->n_near;
+    auto bsize = [&](int64_t i) {
+        return (d->end[d->near_t[i]] - d->begin[d->near_t[i]]) * (d->end[d->near_s[i]] - d->begin[d->near_s[i]]);
+    };
+    auto identity = [&]() {
+        P.near_uoff.assign(d->near_off, d->near_off + nn);
+        P.near_src.clear();
+        P.near_stored_len = d->near_len;
+        P.near_dedup = false;
+    };
+    if (!allow || nn == 0) {
+        identity();
+        return;
+    }
+    std::vector<uint64_t> hash(nn);
+    auto hash_range = [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+            const uint64_t* w = reinterpret_cast<const uint64_t*>(d->near_blocks + 2 * d->near_off[i]);
+            const int64_t nw = 2 * bsize(i);
+            uint64_t h = 0x9e3779b97f4a7c15ull ^ uint64_t(nw);
+            for (int64_t k = 0; k < nw; ++k) {
+                h ^= w[k];
+                h *= 0x100000001b3ull;
+                h ^= h >> 29;
+            }
+            hash[i] = h;
+        }
+    };
+    const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(8, nn / 1024 + 1));
+    {
+        std::vector<std::thread> th;
+        for (int64_t k = 0; k < nth; ++k) th.emplace_back(hash_range, nn * k / nth, nn * (k + 1) / nth);
+        for (auto& x : th) x.join();
+    }
+    // representative of each (size, hash): the first block that has it
+    std::map<std::pair<int64_t, uint64_t>, int64_t> first;
+    std::vector<int64_t> rep(nn);
+    for (int64_t i = 0; i < nn; ++i) {
+        auto it = first.emplace(std::make_pair(bsize(i), hash[i]), i).first;
+        rep[i] = it->second;
+    }
+    // confirm every match bit for bit
+    std::vector<char> same(nn, 1);
+    auto confirm = [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i)
+            if (rep[i] != i)
+                same[i] = std::memcmp(d->near_blocks + 2 * d->near_off[i], d->near_blocks + 2 * d->near_off[rep[i]],
+                                      size_t(bsize(i)) * 16) == 0;
+    };
+    {
+        std::vector<std::thread> th;
+        for (int64_t k = 0; k < nth; ++k) th.emplace_back(confirm, nn * k / nth, nn * (k + 1) / nth);
+        for (auto& x : th) x.join();
+    }
+    P.near_uoff.assign(nn, -1);
+    P.near_src.clear();
+    int64_t stored = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        if (rep[i] != i && same[i]) {
+            P.near_uoff[i] = P.near_uoff[rep[i]];
+            continue;
+        }
+        P.near_uoff[i] = stored;
+        P.near_src.push_back(i);
+        stored += bsize(i);
+    }
+    if (2 * stored > d->near_len) {
+        identity();
+        return;
+    }
+    P.near_stored_len = stored;
+    P.near_dedup = true;
+}
+
 // Symmetric near field.  G is symmetric (G_ij = G_ji), so when the description's
 // blocks satisfy G_st = G_ts^T bit for bit, each unordered leaf pair {t, s} is
 // streamed once by one of its two leaves (the owner, chosen to balance the blocks
@@ -264,14 +350,14 @@ static void plan_symmetric_near(const h2_host_desc* d, const std::vector<int64_t
             if (d->near_s[i] == t) {
                 P.sym_sbeg.push_back(int(d->begin[t]));
                 P.sym_ssize.push_back(size(t));
-                P.sym_off.push_back(d->near_off[i]);
+                P.sym_off.push_back(P.near_uoff[i]);
                 P.sym_pslot.push_back(-1);
             }
         for (auto& o : own[t]) {
             const int other = d->near_s[o.first];
             P.sym_sbeg.push_back(int(d->begin[other]));
             P.sym_ssize.push_back(size(other));
-            P.sym_off.push_back(d->near_off[o.first]);
+            P.sym_off.push_back(P.near_uoff[o.first]);
             P.sym_pslot.push_back(o.second);
         }
         P.sym_ptr.push_back(int(P.sym_off.size()));
@@ -288,7 +374,9 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     if (!o) return fail(H2_ERR_INVALID_ARG, "null build options");
     if (o->max_rhs < 1) return fail(H2_ERR_INVALID_ARG, "max_rhs must be >= 1");
     if (o->tiers & ~7) return fail(H2_ERR_INVALID_ARG, "unknown tier bits 0x%x", o->tiers);
+    if (o->flags & ~H2_BUILD_KEEP_ALL_NEAR) return fail(H2_ERR_INVALID_ARG, "unknown build flags 0x%x", o->flags);
     P.tiers = o->tiers | 1;
+    plan_near_dedup(d, (o->flags & H2_BUILD_KEEP_ALL_NEAR) == 0, P);
     const int nc = d->n_clusters;
     const int64_t n = d->n_vox;
     P.perm.assign(n, 0);
@@ -337,7 +425,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
             int s = d->near_s[i];
             P.near_sbeg.push_back(int(d->begin[s]));
             P.near_ssize.push_back(int(d->end[s] - d->begin[s]));
-            P.near_off.push_back(d->near_off[i]);
+            P.near_off.push_back(P.near_uoff[i]);
         }
         if (P.near_off.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many near blocks");
         P.near_ptr.push_back(int(P.near_off.size()));
@@ -351,7 +439,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         const int n = int(d->end[c] - d->begin[c]);
         int64_t diag = -1;
         for (int64_t i = nfirst[c]; i < nfirst[c] + ncount[c]; ++i)
-            if (d->near_s[i] == c) diag = d->near_off[i];
+            if (d->near_s[i] == c) diag = P.near_uoff[i];
         if (diag < 0) return fail(H2_ERR_BAD_DESC, "leaf %d has no diagonal near block", c);
         P.lc_beg.push_back(int(d->begin[c]));
         P.lc_size.push_back(n);
@@ -440,13 +528,14 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
     for (int tier = 0; tier < 3; ++tier)
         for (int q = 0; q < 4; ++q) P.o_data[tier][q] = 0;
-    for (int q = 0; q < 4; ++q) P.o_data[0][q] = L.add(std::max<int64_t>(lens[q], 1) * 16);
+    const int64_t held[4] = {P.near_stored_len, lens[1], lens[2], lens[3]};
+    for (int q = 0; q < 4; ++q) P.o_data[0][q] = L.add(std::max<int64_t>(held[q], 1) * 16);
     if (P.tiers & 2)
-        for (int q = 0; q < 4; ++q) P.o_data[1][q] = L.add(std::max<int64_t>(lens[q], 1) * 8);
+        for (int q = 0; q < 4; ++q) P.o_data[1][q] = L.add(std::max<int64_t>(held[q], 1) * 8);
     if (P.tiers & 4) {
         P.batch = new BatchHost();
         BatchHost& B = *P.batch;
-        h2_status bs = plan_batch(d, o->max_rhs, B);
+        h2_status bs = plan_batch(d, o->max_rhs, P.near_uoff.data(), B);
         if (bs != H2_OK) return fail(bs, "batched tier needs ranks <= 64 and fewer than 2^31 padded rows");
         const size_t cols = size_t(B.max_cols);
         P.o_arena = L.add(size_t(std::max<int64_t>(B.arena_elems, 1)) * 2);
@@ -544,19 +633,34 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         errs.push_back(put(P.o_symoff, P.sym_off.data(), P.sym_off.size() * 8));
     }
     const double* src[4] = {d->near_blocks, d->coupling, d->basis, d->transfer};
-    const int64_t lens[4] = {d->near_len, d->coupling_len, d->basis_len, d->transfer_len};
+    const int64_t lens[4] = {P.near_stored_len, d->coupling_len, d->basis_len, d->transfer_len};
+    std::vector<double> near_staged;        // the stored near blocks, gathered (identical blocks once)
+    if (P.near_dedup) {
+        near_staged.resize(size_t(2 * P.near_stored_len));
+        for (int64_t i : P.near_src) {
+            const int64_t n = (d->end[d->near_t[i]] - d->begin[d->near_t[i]]) * (d->end[d->near_s[i]] - d->begin[d->near_s[i]]);
+            std::memcpy(near_staged.data() + 2 * P.near_uoff[i], d->near_blocks + 2 * d->near_off[i], size_t(n) * 16);
+        }
+        src[0] = near_staged.data();
+    }
     for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_data[0][q], src[q], size_t(lens[q]) * 16));
     for (hipError_t e : errs)
-        if (e != hipSuccess) return fail(H2_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);     // no copy may still read the host staging
+            return fail(H2_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+        }
     // lower-precision tiers converted on the device from the FP64 copy
     for (int q = 0; q < 4; ++q) {
         if (lens[q] == 0) continue;
         if (P.tiers & 2) {
             hipError_t e = launch_convert_fp32((const double2*)(base + P.o_data[0][q]), (float2*)(base + P.o_data[1][q]), lens[q], s);
-            if (e != hipSuccess) return fail(H2_ERR_DEVICE, "fp32 conversion failed: %s", hipGetErrorString(e));
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(s);
+                return fail(H2_ERR_DEVICE, "fp32 conversion failed: %s", hipGetErrorString(e));
+            }
         }
     }
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = hipStreamSynchronize(s);       // also the last read of the near staging
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "build synchronisation failed: %s", hipGetErrorString(e));
 
     h2_handle h = new h2_handle_s();
@@ -600,9 +704,12 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.leaves.inv_elems = P.lc_inv_elems;
     D.leaves.max_leaf = P.lc_max;
     D.down_list = (const int*)(base + P.o_down);
+    D.near_cached = P.near_dedup;
     if (P.sym) {
         D.near_sym_ok = true;
-        D.near_sym = true;
+        // halving the block stream pays when the blocks come from HBM; blocks stored
+        // once are read from the caches, where the one-sided full mode is faster
+        D.near_sym = !P.near_dedup;
         D.sym_leaf = (const int*)(base + P.o_sym[0]);
         D.sym_ptr = (const int*)(base + P.o_sym[1]);
         D.sym_sbeg = (const int*)(base + P.o_sym[2]);
@@ -672,6 +779,8 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     S.n_near = d->n_near;
     S.depth = P.depth;
     S.near_elems = d->near_len;
+    S.near_stored_elems = P.near_stored_len;
+    S.near_unique = P.near_dedup ? int64_t(P.near_src.size()) : d->n_near;
     S.coupling_elems = d->coupling_len;
     S.basis_elems = d->basis_len;
     S.transfer_elems = d->transfer_len;

@@ -29,10 +29,10 @@ def test_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-def _plan(d, max_rhs=1, tiers=1):
+def _plan(d, max_rhs=1, tiers=1, flags=0):
     lib = _lib_or_build()
     hd, keep = _lib.host_desc(d)
-    opts = _lib.BuildOpts(max_rhs=max_rhs, tiers=tiers)
+    opts = _lib.BuildOpts(max_rhs=max_rhs, tiers=tiers, flags=flags)
     n = C.c_size_t(0)
     st = lib.h2_plan_from_host(C.byref(hd), C.byref(opts), C.byref(n))
     return st, n.value
@@ -45,25 +45,62 @@ def desc():
 
 
 def test_plan_ok(desc):
-    st, n = _plan(desc)
+    st, n = _plan(desc, flags=1)
     assert st == 0 and n > desc.near.nbytes + desc.coupling.nbytes
-    st2, n2 = _plan(desc, tiers=3)
+    st2, n2 = _plan(desc, tiers=3, flags=1)
     assert st2 == 0 and n2 > n
+    st3, n3 = _plan(desc)
+    assert st3 == 0 and n3 < n
 
 
 def test_plan_reserves_partials_only_for_symmetric_near_blocks(desc):
     """The plan checks G_st = G_ts^T bit for bit on the host: the symmetric near
     mode's partial slots (one 64 x 3 complex slot per unordered leaf pair) are
     reserved for the generated description and not once one entry is changed."""
-    st, n = _plan(desc)
+    st, n = _plan(desc, flags=1)
     i = int(np.nonzero(desc.near_t != desc.near_s)[0][0])
     e = copy.copy(desc)
     e.near = desc.near.copy()
     e.near[desc.near_off[i] + 1] *= 1.5
-    st2, n2 = _plan(e)
+    st2, n2 = _plan(e, flags=1)
     pairs = int((desc.near_t != desc.near_s).sum()) // 2
     assert st == 0 and st2 == 0
     assert n - n2 >= pairs * 64 * 3 * 16 + 16 * desc.n_vox * 3
+
+
+def _unique_near(d):
+    """Distinct near blocks (size and bytes), counted by brute force."""
+    size = d.end - d.begin
+    seen = {}
+    for i in range(len(d.near_t)):
+        n = int(size[d.near_t[i]] * size[d.near_s[i]])
+        seen.setdefault((n, d.near[d.near_off[i]:d.near_off[i] + n].tobytes()), n)
+    return len(seen), sum(seen.values())
+
+
+def test_plan_stores_identical_near_blocks_once():
+    """cube12: 2680 near pairs over 117 distinct blocks.  The plan holds each
+    distinct block once (the device buffer shrinks by the entries saved), unless
+    asked to keep every block; an unknown flag is rejected."""
+    from conftest import built
+    d = built("cube12")[1]
+    n_unique, stored = _unique_near(d)
+    assert n_unique == 117
+    st, n = _plan(d)
+    st2, n2 = _plan(d, flags=1)
+    assert st == 0 and st2 == 0
+    assert n2 - n >= 16 * (d.near.size - stored) - 4096
+    assert _plan(d, flags=2)[0] == -1
+
+
+def test_plan_keeps_near_blocks_when_few_repeat():
+    """box9 repeats too few blocks for storing them once to halve the storage: the
+    plan is the same with and without the flag."""
+    from conftest import built
+    d = built("box9")[1]
+    n_unique, stored = _unique_near(d)
+    assert 2 * stored > d.near.size
+    assert _plan(d)[1] == _plan(d, flags=1)[1]
 
 
 def _corrupt(desc, field, fn):

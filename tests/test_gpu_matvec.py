@@ -134,7 +134,9 @@ def test_symmetric_near_mode_matches_full_mode_and_oracle(torch, name):
     FP32, and agree with each other to rounding."""
     print(f"[gpu] near modes {name}", flush=True)
     g, d, H = operator(name)
-    assert H.near_mode() == (True, True)
+    stored_once = H.stats()["near_stored_elems"] < H.stats()["near_elems"]
+    assert H.near_mode() == (not stored_once, True)     # the default: symmetric unless blocks are cached
+    assert H.near_mode(True) == (True, True)
     x = h2gen.random_vector(3 * g.n_vox, 23)
     xs = torch.from_numpy(x).cuda()
     ys = H.matvec(xs).cpu().numpy()
@@ -142,7 +144,7 @@ def test_symmetric_near_mode_matches_full_mode_and_oracle(torch, name):
     assert H.near_mode(False) == (False, True)
     yf = H.matvec(xs).cpu().numpy()
     yf32f = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
-    H.near_mode(True)
+    H.near_mode(not stored_once)
     yo = om.h2_matvec(d, x)
     assert _rel(ys, yo) <= 1e-12 and _rel(yf, yo) <= 1e-12
     assert _rel(ys, yf) <= 1e-13
@@ -168,3 +170,42 @@ def test_asymmetric_near_blocks_use_the_full_mode(torch):
     y = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     assert _rel(y, om.h2_matvec(d2, x)) <= 1e-12
     H.close()
+
+
+@pytest.mark.parametrize("name", ["cube12", "slab"])
+def test_identical_near_blocks_stored_once_give_identical_products(torch, name):
+    """Storing identical near blocks once (and reading them through the caches)
+    changes no arithmetic: every product equals, bit for bit, the one of an
+    operator built with every near block kept, in FP64 (both near modes), FP32,
+    several right-hand sides per pass and BF16x3; both match the oracle."""
+    from paper_1703_01175_amd import H2Operator
+    print(f"[gpu] stored-once near blocks {name}", flush=True)
+    g, d = built(name)
+    tiers = ("fp64", "fp32", "bf16x3")
+    A = H2Operator(d, tiers=tiers, max_rhs=4)
+    B = H2Operator(d, tiers=tiers, max_rhs=4, keep_all_near=True)
+    sa, sb = A.stats(), B.stats()
+    assert sa["near_unique"] < sa["n_near"] and 2 * sa["near_stored_elems"] <= sa["near_elems"]
+    assert sb["near_unique"] == sb["n_near"] and sb["near_stored_elems"] == sb["near_elems"]
+    x = h2gen.random_vector(3 * g.n_vox, 31)
+    X = h2gen.random_vector(3 * g.n_vox, 32, ncols=4)
+    x32 = torch.from_numpy(x.astype(np.complex64)).cuda()
+    for sym in (True, False):
+        A.near_mode(sym)
+        B.near_mode(sym)
+        ya = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        yb = B.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.array_equal(ya, yb), sym
+        assert _rel(ya, om.h2_matvec(d, x)) <= 1e-12
+        assert np.array_equal(A.matvec(x32, precision="fp32").cpu().numpy(),
+                              B.matvec(x32, precision="fp32").cpu().numpy()), sym
+    Ya = A.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yb = B.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.array_equal(Ya, Yb)
+    X32 = torch.from_numpy(X.astype(np.complex64)).cuda()
+    Za = A.matvec(X32, precision="bf16x3").cpu().numpy()
+    Zb = B.matvec(X32, precision="bf16x3").cpu().numpy()
+    assert np.array_equal(Za, Zb)
+    assert _rel(Za[2], om.h2_matvec(d, X[2])) <= 1e-4
+    A.close()
+    B.close()
