@@ -12,6 +12,7 @@ constexpr int kMaxLeaf = 64;     // voxels per leaf cluster
 constexpr int kMrRhs = 4;        // right-hand sides per pass of the multi-RHS FP64 / FP32 product
 constexpr int kMrCols = kNcomp * kMrRhs;
 constexpr int kMaxRank = 256;    // cluster rank limit
+constexpr int64_t kNearPassBytes = int64_t(2) << 20;   // distinct near-block bytes per near-field pass
 
 // Storage tier of the block data (near blocks, couplings, bases, transfers).
 struct TierData {
@@ -80,6 +81,9 @@ struct DevH2 {
     const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)
 
     bool near_cached = false;           // identical near blocks stored once: read them through the caches
+    int near_passes = 1;                // full-mode near launches, each over a share of the distinct blocks
+    const int* near_pass_ptr = nullptr; // [n_leaves][near_passes + 1] list ranges of each pass
+    void* near_ypart = nullptr;         // [n_vox][3] tree order: rows summed by the earlier passes
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
     bool near_sym = false;              // products use it (selectable while near_sym_ok)

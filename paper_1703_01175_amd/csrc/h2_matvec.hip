@@ -280,8 +280,12 @@ __global__ __launch_bounds__(64) void k_transfer_down(const int* __restrict__ li
 // ---------------------------------------------------------------- near field + leaf backward + epilogue
 // One 256-thread group per leaf t; wave w streams near blocks w, w+4, ...;
 // lane i owns row i of every block (column-major blocks: coalesced columns).
+// With several passes (pass_ptr set), this launch covers pass `pass` of the
+// leaf's blocks: the earlier passes leave their row sums in ypart (tree order),
+// the last one adds them and finishes.
 template <typename TB, typename TV, bool NT>
 __global__ __launch_bounds__(256) void k_near_epilogue(
+    const int* __restrict__ pass_ptr, int pass, int npass, TV* __restrict__ ypart,
     const int* __restrict__ leaf_id, const int* __restrict__ near_ptr, const int* __restrict__ near_sbeg,
     const int* __restrict__ near_ssize, const int64_t* __restrict__ near_off, const TB* __restrict__ near,
     const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
@@ -297,8 +301,9 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
     // come through scalar loads, and only the block stream uses vector loads
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
-    const int e = near_ptr[slot + 1];
-    for (int blk = near_ptr[slot] + w; blk < e; blk += 4) {
+    const int b0 = pass_ptr ? pass_ptr[slot * (npass + 1) + pass] : near_ptr[slot];
+    const int e = pass_ptr ? pass_ptr[slot * (npass + 1) + pass + 1] : near_ptr[slot + 1];
+    for (int blk = b0 + w; blk < e; blk += 4) {
         const int sb = near_sbeg[blk];
         const int ns = near_ssize[blk];
         const TB* Gb = near + near_off[blk] + lane;
@@ -319,6 +324,20 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
         TV s0 = cadd(cadd(red[0][lane][0], red[1][lane][0]), cadd(red[2][lane][0], red[3][lane][0]));
         TV s1 = cadd(cadd(red[0][lane][1], red[1][lane][1]), cadd(red[2][lane][1], red[3][lane][1]));
         TV s2 = cadd(cadd(red[0][lane][2], red[1][lane][2]), cadd(red[2][lane][2], red[3][lane][2]));
+        if (npass > 1) {   // rows of the earlier passes; all but the last pass stop here
+            TV* yp = ypart + (int64_t)(cl_begin[t] + lane) * kNcomp;
+            if (pass > 0) {
+                s0 = cadd(yp[0], s0);
+                s1 = cadd(yp[1], s1);
+                s2 = cadd(yp[2], s2);
+            }
+            if (pass < npass - 1) {
+                yp[0] = s0;
+                yp[1] = s1;
+                yp[2] = s2;
+                return;
+            }
+        }
         const int k = cl_rank[t];
         if (k > 0) {   // backward transformation at the leaf: y_t += V_t Y_t
             const TB* V = basis + cl_basis_off[t];
@@ -599,9 +618,12 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             end(6);
         } else {
             auto kn = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
-            kn<<<d.n_leaves, 256, 0, s>>>(d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near,
-                                          d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh,
-                                          d.perm, xr, yr, op, alpha);
+            const int np = d.near_passes;
+            for (int pass = 0; pass < np; ++pass)
+                kn<<<d.n_leaves, 256, 0, s>>>(np > 1 ? d.near_pass_ptr : nullptr, pass, np, (TV*)d.near_ypart,
+                                              d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near,
+                                              d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U,
+                                              Yh, d.perm, xr, yr, op, alpha);
             end(5);
         }
     }

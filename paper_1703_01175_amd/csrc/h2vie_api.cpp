@@ -61,6 +61,12 @@ struct Plan {
     std::vector<int64_t> near_src;
     int64_t near_stored_len = 0;
     bool near_dedup = false;
+    // stored-once near blocks split into passes of about kNearPassBytes of distinct blocks
+    // each (so one pass's blocks stay in an XCD's L2); pass p of launch slot q covers the
+    // list entries [near_pass_ptr[q (P + 1) + p], near_pass_ptr[q (P + 1) + p + 1])
+    int near_passes = 1;
+    std::vector<int> near_pass_ptr;
+    size_t o_npass = 0, o_ypart = 0;
     // symmetric near field: each unordered leaf pair once (empty when G_st != G_ts^T somewhere)
     bool sym = false;
     int64_t sym_pairs = 0;
@@ -419,14 +425,33 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     }
     std::stable_sort(leaves.begin(), leaves.end(), [&](int a, int b) { return ncount[a] > ncount[b]; });
     P.leaf_id = leaves;
+    // passes over the stored-once blocks: distinct blocks by use count, dealt in turn
+    // to the passes (which evens out both their bytes and their work)
+    std::map<int64_t, int> pass_of;                  // stored offset -> pass
+    if (P.near_dedup) {
+        const int64_t bytes = 16 * P.near_stored_len;
+        P.near_passes = int(std::min<int64_t>(8, std::max<int64_t>(1, (bytes + kNearPassBytes - 1) / kNearPassBytes)));
+        std::map<int64_t, int64_t> uses;
+        for (int64_t i = 0; i < d->n_near; ++i) uses[P.near_uoff[i]]++;
+        std::vector<std::pair<int64_t, int64_t>> order(uses.begin(), uses.end());
+        std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.second > b.second; });
+        for (size_t k = 0; k < order.size(); ++k) pass_of[order[k].first] = int(k % P.near_passes);
+    }
+    const int np = P.near_passes;
     P.near_ptr.assign(1, 0);
+    P.near_pass_ptr.clear();
     for (int t : leaves) {
-        for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i) {
-            int s = d->near_s[i];
-            P.near_sbeg.push_back(int(d->begin[s]));
-            P.near_ssize.push_back(int(d->end[s] - d->begin[s]));
-            P.near_off.push_back(P.near_uoff[i]);
+        for (int p = 0; p < np; ++p) {
+            P.near_pass_ptr.push_back(int(P.near_off.size()));
+            for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i) {
+                if (np > 1 && pass_of[P.near_uoff[i]] != p) continue;
+                int s = d->near_s[i];
+                P.near_sbeg.push_back(int(d->begin[s]));
+                P.near_ssize.push_back(int(d->end[s] - d->begin[s]));
+                P.near_off.push_back(P.near_uoff[i]);
+            }
         }
+        P.near_pass_ptr.push_back(int(P.near_off.size()));
         if (P.near_off.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many near blocks");
         P.near_ptr.push_back(int(P.near_off.size()));
     }
@@ -506,6 +531,8 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     P.o_nsb = L.add(ints(P.near_sbeg.size()));
     P.o_nss = L.add(ints(P.near_ssize.size()));
     P.o_noff = L.add(i64s(P.near_off.size()));
+    P.o_npass = L.add(ints(P.near_pass_ptr.size()));
+    if (P.near_passes > 1) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
     P.o_rowcl = L.add(ints(P.row_cl.size()));
     P.o_rownc = L.add(ints(P.row_ncols.size()));
     P.o_rowcp = L.add(ints(P.row_colptr.size()));
@@ -615,6 +642,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     errs.push_back(put(P.o_nsb, P.near_sbeg.data(), P.near_sbeg.size() * 4));
     errs.push_back(put(P.o_nss, P.near_ssize.data(), P.near_ssize.size() * 4));
     errs.push_back(put(P.o_noff, P.near_off.data(), P.near_off.size() * 8));
+    errs.push_back(put(P.o_npass, P.near_pass_ptr.data(), P.near_pass_ptr.size() * 4));
     errs.push_back(put(P.o_rowcl, P.row_cl.data(), P.row_cl.size() * 4));
     errs.push_back(put(P.o_rownc, P.row_ncols.data(), P.row_ncols.size() * 4));
     errs.push_back(put(P.o_rowcp, P.row_colptr.data(), P.row_colptr.size() * 4));
@@ -705,6 +733,9 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.leaves.max_leaf = P.lc_max;
     D.down_list = (const int*)(base + P.o_down);
     D.near_cached = P.near_dedup;
+    D.near_passes = P.near_passes;
+    D.near_pass_ptr = (const int*)(base + P.o_npass);
+    D.near_ypart = P.near_passes > 1 ? base + P.o_ypart : nullptr;
     if (P.sym) {
         D.near_sym_ok = true;
         // halving the block stream pays when the blocks come from HBM; blocks stored

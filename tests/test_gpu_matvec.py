@@ -175,9 +175,11 @@ def test_asymmetric_near_blocks_use_the_full_mode(torch):
 @pytest.mark.parametrize("name", ["cube12", "slab"])
 def test_identical_near_blocks_stored_once_give_identical_products(torch, name):
     """Storing identical near blocks once (and reading them through the caches)
-    changes no arithmetic: every product equals, bit for bit, the one of an
-    operator built with every near block kept, in FP64 (both near modes), FP32,
-    several right-hand sides per pass and BF16x3; both match the oracle."""
+    changes no arithmetic beyond the order of the near sums (the full mode runs the
+    leaf's blocks in passes over a share of the distinct blocks each): the
+    symmetric mode and BF16x3 products equal, bit for bit, those of an operator
+    built with every near block kept; the full mode, FP32 and several right-hand
+    sides per pass agree to rounding; both match the oracle."""
     from paper_1703_01175_amd import H2Operator
     print(f"[gpu] stored-once near blocks {name}", flush=True)
     g, d = built(name)
@@ -195,13 +197,14 @@ def test_identical_near_blocks_stored_once_give_identical_products(torch, name):
         B.near_mode(sym)
         ya = A.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
         yb = B.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
-        assert np.array_equal(ya, yb), sym
+        assert np.array_equal(ya, yb) if sym else _rel(ya, yb) <= 1e-14, sym
         assert _rel(ya, om.h2_matvec(d, x)) <= 1e-12
-        assert np.array_equal(A.matvec(x32, precision="fp32").cpu().numpy(),
-                              B.matvec(x32, precision="fp32").cpu().numpy()), sym
+        fa = A.matvec(x32, precision="fp32").cpu().numpy()
+        fb = B.matvec(x32, precision="fp32").cpu().numpy()
+        assert np.array_equal(fa, fb) if sym else _rel(fa, fb) <= 1e-6, sym
     Ya = A.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
     Yb = B.matvec(torch.from_numpy(X).cuda()).cpu().numpy()
-    assert np.array_equal(Ya, Yb)
+    assert _rel(Ya, Yb) <= 1e-14
     X32 = torch.from_numpy(X.astype(np.complex64)).cuda()
     Za = A.matvec(X32, precision="bf16x3").cpu().numpy()
     Zb = B.matvec(X32, precision="bf16x3").cpu().numpy()
