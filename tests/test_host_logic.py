@@ -13,3 +13,30 @@ def test_leaf_neighbors_match_oracle_halo_table(name):
     tab = leaf_neighbors(d, g.shape)
     assert tab.dtype == np.int32
     assert np.array_equal(tab, omlp.halo_table(d, g.shape))
+
+
+@pytest.mark.parametrize("name", ["cube12", "rod", "box9"])
+def test_bench_near_byte_counts(name):
+    """bench.py's algorithmic byte counts of the near field, against a brute-force
+    walk over the near pairs: the symmetric mode streams the blocks with t <= s
+    (each unordered pair once, the diagonal blocks once) and writes one partial
+    of the other leaf's rows per unordered pair; the full mode streams them all."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    g, d = built(name)
+    size = (d.end - d.begin).astype(np.int64)
+    owned = 0
+    other = 0.0
+    for t, s in zip(d.near_t, d.near_s):
+        if t <= s:
+            owned += int(size[t] * size[s])
+        if t < s:
+            other += 0.5 * (size[t] + size[s])
+    assert bench.near_sym_owned(d) == owned
+    main, finish = bench.near_sym_bytes(d)
+    n3 = 3 * g.n_vox
+    assert main == pytest.approx(16.0 * owned + 48.0 * other + 32.0 * n3)
+    assert finish == pytest.approx(48.0 * other + 16.0 * d.basis.size + 48.0 * n3)
+    assert bench.near_kernel_bytes(d) == 16.0 * (d.near.size + d.basis.size) + 48.0 * n3
