@@ -82,19 +82,37 @@ def near_sym_owned(d) -> float:
     return (float(d.near.size) + float((size[d.nchild == 0] ** 2).sum())) / 2.0
 
 
+def kernel_source_sha(src: str, kernel: str):
+    """sha256 prefix of one __global__ function's text in a HIP source (from its
+    template line to the closing brace at column 0), or None if absent."""
+    import hashlib
+    lines = src.split("\n")
+    for i, line in enumerate(lines):
+        if f"void {kernel}(" in line and "__global__" in " ".join(lines[max(0, i - 1):i + 1]):
+            a = i - 1 if lines[i - 1].startswith("template") else i
+            b = next(j for j in range(i, len(lines)) if lines[j] == "}")
+            return hashlib.sha256("\n".join(lines[a:b + 1]).encode()).hexdigest()[:16]
+    return None
+
+
 def measured_traffic(workload: str, kernel: str = "k_near_epilogue"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel
-    source is unchanged since the counters were taken (else None)."""
+    is unchanged since the counters were taken (else None): the record names either
+    the whole source file's hash or the kernel function's own."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_counters_{workload}_fp64.md")
     src = os.path.join(ROOT, "paper_1703_01175_amd", "csrc", "h2_matvec.hip")
     if not os.path.exists(path):
         return None
+    text = open(src, "rb").read()
+    sha = hashlib.sha256(text).hexdigest()[:16]
+    ksha = kernel_source_sha(text.decode(), kernel)
     for line in open(path):
         if line.startswith("traffic-json: "):
             j = json.loads(line[len("traffic-json: "):])
-            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-            if j.get("kernel") == kernel and j.get("source_sha256_prefix") == sha:
+            if j.get("kernel") != kernel:
+                continue
+            if j.get("source_sha256_prefix") == sha or (ksha and j.get("kernel_sha256_prefix") == ksha):
                 return float(j["traffic_bytes"])
     return None
 
@@ -195,10 +213,8 @@ def main():
     for _ in range(args.warmup):
         H.matvec(x, out=y)
     torch.cuda.synchronize()
-    assert H.lib.h2_profile_enable(H.handle, 1) == 0
-    import ctypes as C
-    buf = (C.c_byte * 128)()
-    H.lib.h2_profile_read(H.handle, buf)       # reset
+    # the timed region: products as the library runs them (with stored-once near blocks
+    # the early near passes overlap the couplings on a side stream)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -208,6 +224,15 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
+    # per-kernel-family durations: the same products again with the library's HIP events
+    # around each family (which keeps the families in order on the product's stream)
+    assert H.lib.h2_profile_enable(H.handle, 1) == 0
+    import ctypes as C
+    buf = (C.c_byte * 128)()
+    H.lib.h2_profile_read(H.handle, buf)       # reset
+    for _ in range(args.steps):
+        H.matvec(x, out=y)
+    torch.cuda.synchronize()
     assert H.lib.h2_profile_read(H.handle, buf) == 0
     fam_ms = np.frombuffer(bytes(buf)[:64], np.float64).copy()
     fam_n = np.frombuffer(bytes(buf)[64:], np.int64).copy()

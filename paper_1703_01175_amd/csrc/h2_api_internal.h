@@ -120,6 +120,9 @@ struct h2_handle_s {
     float* halo_means = nullptr;        // n_leaves x 6 scaled leaf means of the current input, library memory
     int halo_slots = 0;
     ~h2_handle_s() {
+        if (dev.near_side) (void)hipStreamDestroy(dev.near_side);
+        if (dev.near_fork) (void)hipEventDestroy(dev.near_fork);
+        if (dev.near_join) (void)hipEventDestroy(dev.near_join);
         if (halo_nbr) (void)hipFree(halo_nbr);
         if (halo_means) (void)hipFree(halo_means);
         if (self_group) h2::group_destroy(self_group);

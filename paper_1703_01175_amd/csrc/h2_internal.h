@@ -84,6 +84,10 @@ struct DevH2 {
     int near_passes = 1;                // full-mode near launches, each over a share of the distinct blocks
     const int* near_pass_ptr = nullptr; // [n_leaves][near_passes + 1] list ranges of each pass
     void* near_ypart = nullptr;         // [n_vox][3] tree order: rows summed by the earlier passes
+    // the earlier passes need only U: they run on a side stream while the product's
+    // stream runs the upward pass, the couplings and the downward pass (unset: in order)
+    hipStream_t near_side = nullptr;
+    hipEvent_t near_fork = nullptr, near_join = nullptr;
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
     bool near_sym = false;              // products use it (selectable while near_sym_ok)

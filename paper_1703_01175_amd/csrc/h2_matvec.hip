@@ -574,12 +574,31 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     const R alpha = (R)(d.sigma * d.k * d.k * d.volume);
     auto begin = [&](int f) { if (prof) prof->begin(f, s); };
     auto end = [&](int f) { if (prof) prof->end(f, s); };
+    // full mode over stored-once blocks: all passes but the last read only U, so they
+    // run on the side stream beside the upward pass, couplings and downward pass
+    // (kept in order when the kernel families are being timed)
+    const bool overlap = !prof && !d.near_sym && d.near_passes > 1 && d.near_side;
+    auto near_kernel = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
+    auto near_pass = [&](int pass, const TV* xr, TV* yr, hipStream_t st) {
+        const int np = d.near_passes;
+        near_kernel<<<d.n_leaves, 256, 0, st>>>(np > 1 ? d.near_pass_ptr : nullptr, pass, np, (TV*)d.near_ypart,
+                                                d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near,
+                                                d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U,
+                                                Yh, d.perm, xr, yr, op, alpha);
+    };
     for (int64_t r = 0; r < n_rhs; ++r) {
         const TV* xr = x + r * ld;
         TV* yr = y + r * ld;
         begin(0);
         k_prologue<TV><<<(d.n_vox + 255) / 256, 256, 0, s>>>(d.n_vox, d.perm, d.chi, xr, U, op);
         end(0);
+        if (overlap) {
+            hipError_t e = hipEventRecord(d.near_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(d.near_side, d.near_fork, 0);
+            if (e != hipSuccess) return e;
+            for (int pass = 0; pass + 1 < d.near_passes; ++pass) near_pass(pass, xr, yr, d.near_side);
+            if ((e = hipEventRecord(d.near_join, d.near_side)) != hipSuccess) return e;
+        }
         if (d.coef_rows > 0) {
             begin(1);
             k_leaf_forward<TB, TV><<<d.n_leaves, 64, 0, s>>>(d.leaf_id, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
@@ -616,14 +635,13 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                 d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis,
                                                                 Yh, d.perm, xr, yr, op, alpha);
             end(6);
+        } else if (overlap) {
+            hipError_t e = hipStreamWaitEvent(s, d.near_join, 0);
+            if (e != hipSuccess) return e;
+            near_pass(d.near_passes - 1, xr, yr, s);
+            end(5);
         } else {
-            auto kn = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
-            const int np = d.near_passes;
-            for (int pass = 0; pass < np; ++pass)
-                kn<<<d.n_leaves, 256, 0, s>>>(np > 1 ? d.near_pass_ptr : nullptr, pass, np, (TV*)d.near_ypart,
-                                              d.leaf_id, d.near_ptr, d.near_sbeg, d.near_ssize, d.near_off, near,
-                                              d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U,
-                                              Yh, d.perm, xr, yr, op, alpha);
+            for (int pass = 0; pass < d.near_passes; ++pass) near_pass(pass, xr, yr, s);
             end(5);
         }
     }

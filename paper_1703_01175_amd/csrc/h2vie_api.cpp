@@ -736,6 +736,22 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.near_passes = P.near_passes;
     D.near_pass_ptr = (const int*)(base + P.o_npass);
     D.near_ypart = P.near_passes > 1 ? base + P.o_ypart : nullptr;
+    if (P.near_passes > 1) {   // side stream (default priority) for the passes that need only U
+        hipStream_t side = nullptr;
+        hipEvent_t ef = nullptr, ej = nullptr;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&ef, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ej, hipEventDisableTiming) == hipSuccess) {
+            D.near_side = side;
+            D.near_fork = ef;
+            D.near_join = ej;
+        } else {   // no overlap: the passes run in order on the product's stream
+            if (side) (void)hipStreamDestroy(side);
+            if (ef) (void)hipEventDestroy(ef);
+            if (ej) (void)hipEventDestroy(ej);
+            (void)hipGetLastError();
+        }
+    }
     if (P.sym) {
         D.near_sym_ok = true;
         // halving the block stream pays when the blocks come from HBM; blocks stored
