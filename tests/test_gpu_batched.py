@@ -47,7 +47,11 @@ def test_bf16x3_product(torch, name, nrhs):
         yo = om.h2_matvec(d, X[r])
         emu = oprec.h2_matvec_tier(d, X[r], "bf16x3")
         e, ee = _rel(Y[r], yo), _rel(emu, yo)
-        assert e <= 1e-4 and e <= 3.0 * ee + 1e-6, (r, e, ee)
+        dev = _rel(Y[r], emu)      # device against the emulation of its own arithmetic
+        print(f"[gpu] bf16x3 {name} col {r}: error {e:.3e}, emulated {ee:.3e}, device-emulation {dev:.3e}",
+              flush=True)
+        assert e <= 1e-4 and e <= 2.0 * ee, (r, e, ee)
+        assert dev <= 0.5 * ee, (r, dev, ee)
 
 
 def test_bf16x3_op_g(torch):
