@@ -167,7 +167,7 @@ typedef enum {
 } h2_precond;
 
 typedef struct {
-    int32_t restart;        /* Krylov dimension m per cycle (1..128); 50 */
+    int32_t restart;        /* Krylov dimension m per cycle (1..127); 50 */
     int32_t max_matvec;     /* budget of products with Z */
     double tol;             /* relative residual ||b - Z x|| / ||b|| */
     int32_t precision;      /* h2_precision of the inner products (FP64 = plain GMRES) */
@@ -185,7 +185,7 @@ typedef struct {
     int32_t outer;          /* refinement steps (0 for FP64) */
     double rel_residual;    /* true ||b - Z x|| / ||b||, FP64 product */
     int32_t corrections;    /* accepted learned restart corrections (PRECOND_MLP_RESTART) */
-    int32_t pad;
+    int32_t reorth;         /* Arnoldi steps that took a second Gram-Schmidt pass */
 } h2_gmres_report;
 
 /* Workspace bytes for h2_gmres_solve with opts o (device memory, caller owned). */
@@ -193,8 +193,10 @@ h2_status h2_gmres_workspace(h2_handle h, const h2_gmres_opts* o, size_t* bytes)
 
 /* Solve Z x = b for one right-hand side by restarted GMRES(m) from x0 = 0 (or
  * the given x with use_x0 = 1; restarting from a saved iterate resumes a solve):
- * Arnoldi by classical Gram-Schmidt applied twice, Givens rotations on the
- * Hessenberg matrix, all on the device in FP64; the true residual b - Z x is
+ * Arnoldi by classical Gram-Schmidt with a second pass only when the first left
+ * less than 1/sqrt(2) of ||w|| (the Daniel-Gragg-Kaufman-Stewart test; the
+ * count is rep->reorth), Givens rotations on the Hessenberg matrix, all on the
+ * device in FP64; the true residual b - Z x is
  * formed after every cycle and decides convergence.  With precision FP32 or
  * BF16X3 the solve is iterative refinement: r = b - Z x in FP64, an inner
  * GMRES in FP64 arithmetic whose products use the lower-precision blocks,
@@ -221,7 +223,8 @@ h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, double tol, int
 
 /* Solve Z x_c = b_c for n_rhs right-hand sides at once (the paper's many
  * right-hand sides, Sec. IV.D): every column runs its own restarted GMRES (FP64
- * Arnoldi, CGS2, Givens, own basis and Hessenberg matrix) in lockstep with the
+ * Arnoldi with the same selective second Gram-Schmidt pass, per column, Givens,
+ * own basis and Hessenberg matrix) in lockstep with the
  * others, so that each product is one multi-column product.  precision FP64:
  * plain restarted GMRES; FP32 / BF16X3: iterative refinement with the outer
  * residual b_c - Z x_c in FP64 and the inner solves (to inner_tol relative to

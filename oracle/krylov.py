@@ -5,8 +5,11 @@ Sec. IV.B inside the iteration (BiCGStab at tolerance 1e-3 in Sec. V).  The
 hot path here uses restarted GMRES(m); these are the reference versions:
 
 * gmres: right-preconditioned, optionally flexible (the preconditioner may
-  change between steps), Arnoldi by classical Gram-Schmidt applied twice,
-  the Hessenberg matrix reduced by complex Givens rotations, x0 = 0 unless
+  change between steps), Arnoldi by classical Gram-Schmidt with selective
+  reorthogonalisation (ortho="dgks", the default: a second pass only when the
+  first left less than 1/sqrt(2) of ||w||, the Daniel-Gragg-Kaufman-Stewart
+  test) or always twice (ortho="cgs2"), the Hessenberg matrix reduced by
+  complex Givens rotations, x0 = 0 unless
   given; a cycle ends early once the Givens residual estimate reaches the
   tolerance or on breakdown; after every cycle the true residual b - A x is
   formed and decides convergence (relative to ||b||);
@@ -31,6 +34,7 @@ class SolveReport:
     rel_residual: float        # true ||b - A x|| / ||b|| at exit
     history: list = field(default_factory=list)   # Givens estimates per step
     corrections: int = 0       # accepted restart corrections
+    reorth: int = 0            # Arnoldi steps that took a second Gram-Schmidt pass
 
 
 def givens(a: complex, b: complex):
@@ -46,10 +50,16 @@ def givens(a: complex, b: complex):
     return c, s, (a / aa) * rho
 
 
+DGKS = 1.0 / np.sqrt(2.0)   # reorthogonalise when ||w|| drops below this fraction in a pass
+
+
 def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec: int = 10000,
-          x0: np.ndarray | None = None, precond=None, correct=None) -> tuple:
+          x0: np.ndarray | None = None, precond=None, correct=None, ortho: str = "dgks") -> tuple:
     """Solve A x = b.  apply(v) -> A v; precond(v) -> z (right preconditioner, may be nonlinear).
-    correct(r) -> c: at every cycle start x + c replaces x when it lowers ||b - A x|| (one product)."""
+    correct(r) -> c: at every cycle start x + c replaces x when it lowers ||b - A x|| (one product).
+    ortho: "dgks" (second Gram-Schmidt pass only when needed) or "cgs2" (always two)."""
+    if ortho not in ("dgks", "cgs2"):
+        raise ValueError(ortho)
     b = np.asarray(b, np.complex128)
     n = b.shape[0]
     bnorm = float(np.linalg.norm(b))
@@ -67,11 +77,12 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
         mv += 1
     m = restart
     corrections = 0
+    reorth = 0
     while True:
         beta = float(np.linalg.norm(r))
         rel = beta / bnorm
         if rel <= tol or mv >= max_matvec:
-            return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections)
+            return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections, reorth)
         if correct is not None:
             xt = x + correct(r)
             rt = b - apply(xt)
@@ -82,7 +93,7 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
                 beta = float(np.linalg.norm(r))
                 rel = beta / bnorm
                 if rel <= tol or mv >= max_matvec:
-                    return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections)
+                    return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections, reorth)
         V = np.zeros((m + 1, n), np.complex128)
         Zs = np.zeros((m, n), np.complex128) if precond is not None else None
         H = np.zeros((m + 1, m), np.complex128)
@@ -99,13 +110,17 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
             w = apply(z)
             mv += 1
             its += 1
-            # classical Gram-Schmidt, twice
+            # classical Gram-Schmidt; a second pass when the first removed most of w
+            before = float(np.linalg.norm(w))
             h = V[:j + 1].conj() @ w
             w = w - h @ V[:j + 1]
-            h2 = V[:j + 1].conj() @ w
-            w = w - h2 @ V[:j + 1]
-            h = h + h2
             hn = float(np.linalg.norm(w))
+            if ortho == "cgs2" or not hn >= DGKS * before:
+                reorth += 1
+                h2 = V[:j + 1].conj() @ w
+                w = w - h2 @ V[:j + 1]
+                h = h + h2
+                hn = float(np.linalg.norm(w))
             H[:j + 1, j] = h
             H[j + 1, j] = hn
             for i in range(j):
@@ -136,7 +151,7 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
 
 
 def gmres_ir(apply_hi, apply_lo, b: np.ndarray, tol: float = 1e-6, inner_tol: float = 1e-3,
-             restart: int = 50, max_outer: int = 50, max_matvec: int = 10000):
+             restart: int = 50, max_outer: int = 50, max_matvec: int = 10000, ortho: str = "dgks"):
     """Iterative refinement: r = b - A_hi x; solve A_lo d ~= r to inner_tol; x += d."""
     b = np.asarray(b, np.complex128)
     bnorm = float(np.linalg.norm(b))
@@ -151,7 +166,7 @@ def gmres_ir(apply_hi, apply_lo, b: np.ndarray, tol: float = 1e-6, inner_tol: fl
         rel = float(np.linalg.norm(r)) / bnorm if bnorm > 0 else 0.0
         if rel <= tol:
             break
-        d, rep = gmres(apply_lo, r, tol=inner_tol, restart=restart, max_matvec=max_matvec)
+        d, rep = gmres(apply_lo, r, tol=inner_tol, restart=restart, max_matvec=max_matvec, ortho=ortho)
         inner_its += rep.iterations
         mv_lo += rep.matvecs
         x = x + d

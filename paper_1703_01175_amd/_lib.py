@@ -58,7 +58,7 @@ PRECOND = {"none": 0, "blockdiag": 1, "mlp": 2, "mlp_restart": 3}
 class GmresReport(C.Structure):
     _fields_ = [("converged", C.c_int32), ("iterations", C.c_int32), ("matvecs", C.c_int32),
                 ("restarts", C.c_int32), ("outer", C.c_int32), ("rel_residual", C.c_double),
-                ("corrections", C.c_int32), ("pad", C.c_int32)]
+                ("corrections", C.c_int32), ("reorth", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -25,6 +25,7 @@ class GmresResult:
     outer: int
     rel_residual: float
     corrections: int = 0
+    reorth: int = 0           # Arnoldi steps that took a second Gram-Schmidt pass
 
 
 class H2Operator:
@@ -93,7 +94,7 @@ class H2Operator:
                                      C.byref(rep), C.c_void_p(work.data_ptr()), nbytes, _stream_ptr(stream))
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
-                              rep.rel_residual, rep.corrections)
+                              rep.rel_residual, rep.corrections, rep.reorth)
 
     def bicgstab(self, b, x=None, tol: float = 1e-6, max_matvec: int = 10000, stream=None):
         """Solve Z x = b by FP64 BiCGStab on the device (x0 = 0)."""
@@ -140,7 +141,7 @@ class H2Operator:
                                            _stream_ptr(stream))
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
         return X, [GmresResult(bool(r.converged), r.iterations, r.matvecs, r.restarts, r.outer, r.rel_residual,
-                               r.corrections) for r in reps]
+                               r.corrections, r.reorth) for r in reps]
 
     # ------------------------------------------------------------------ per-leaf preconditioners
     def leaf_count(self):

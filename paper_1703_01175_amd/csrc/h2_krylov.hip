@@ -2,9 +2,10 @@
 //
 // The paper solves its VIE system iteratively with the O(N) H^2 product inside
 // the iteration (Sec. IV.B, Sec. V).  Each Arnoldi step here is
-//   w = Z v_j;  h = V^H w, w -= V h;  h' = V^H w, w -= V h', h += h'  (classical
-//   Gram-Schmidt applied twice);  v_{j+1} = w / ||w||;  Givens update of the
-//   Hessenberg column and of the residual estimate |g_{j+1}|.
+//   w = Z v_j;  h = V^H w, w -= V h  (classical Gram-Schmidt), and when that
+//   left less than 1/sqrt(2) of ||w|| a second pass h' = V^H w, w -= V h',
+//   h += h' (the Daniel-Gragg-Kaufman-Stewart test);  v_{j+1} = w / ||w||;
+//   Givens update of the Hessenberg column and of the residual estimate |g_{j+1}|.
 // A cycle ends at m steps, on breakdown, or when the estimate reaches the
 // tolerance; then y = R^-1 g, x += V y, and the true residual b - Z x decides.
 // With a lower-precision product the solve is iterative refinement: an FP64
@@ -562,6 +563,7 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
         rep->converged = (st == H2_OK);
     }
     rep->corrections = S.corrections;
+    rep->reorth = S.reorth;
     if (hipStreamSynchronize(S.s) != hipSuccess && st >= 0) st = handle_fail(H2_ERR_DEVICE, "solve synchronisation failed");
     (void)hipHostFree(S.host);
     return st;

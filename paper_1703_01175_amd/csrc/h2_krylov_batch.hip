@@ -3,8 +3,9 @@
 // many right-hand sides, Sec. IV.D, Sec. V).
 //
 // Each column keeps its own Krylov basis, Hessenberg matrix, rotations and
-// residual estimate; the Arnoldi arithmetic (classical Gram-Schmidt applied
-// twice, Givens rotations) is FP64 for every product tier.  With the FP32 or
+// residual estimate; the Arnoldi arithmetic (classical Gram-Schmidt, with a
+// second pass for a column whose first pass left less than 1/sqrt(2) of its
+// ||w||, and Givens rotations) is FP64 for every product tier.  With the FP32 or
 // BF16x3 product the solve is iterative refinement: the outer residual
 // b_c - Z x_c is formed with the FP64 product, the inner solve for the
 // correction uses the low-precision product, x_c += d_c.  A column whose
@@ -427,7 +428,7 @@ struct BSolver {
         return H2_OK;
     }
     std::vector<int> corrections;
-    int reorth = 0;                    // lockstep steps that repeated Gram-Schmidt
+    std::vector<int> reorth;           // per column: Arnoldi steps that repeated Gram-Schmidt
 
     void multidot(int nvec, const double2* w, double2* out, int accumulate, const int* nv = nullptr) {   // basis [j][c][ld]
         dim3 grid(nblk, (nvec + kTile - 1) / kTile, ncol);
@@ -502,6 +503,7 @@ struct BSolver {
                     if (grow[c] && !(host[c * kSs + 0] >= kDgks * host[c * kSs + 5])) {
                         again[c] = j + 1;
                         any_again = true;
+                        ++reorth[c];
                     }
                 if (any_again) {
                     if ((st = upload_ints(W.acc, again)) != H2_OK) return st;
@@ -509,7 +511,6 @@ struct BSolver {
                     kb_multiaxpy<<<cgrid(), 256, 0, s>>>(W.V, blk, ld, j + 1, W.acc, W.y, -1.0, W.W, ld, N, W.npart);
                     kb_reduce_add<<<ncol, 128, 0, s>>>(W.hcol, W.y, j + 1);
                     kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 0);
-                    ++reorth;
                 }
                 kb_givens<<<ncol, 64, 0, s>>>(W.H, int64_t(m + 1) * m, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal);
                 if ((st = fetch()) != H2_OK) return st;
@@ -622,6 +623,7 @@ extern "C" h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void
         return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
     S.hjend.assign(ncol, 0);
     S.corrections.assign(ncol, 0);
+    S.reorth.assign(ncol, 0);
     S.hlive.assign(ncol, 1);
     const double2* B = reinterpret_cast<const double2*>(b);
     double2* X = reinterpret_cast<double2*>(x);
@@ -715,6 +717,7 @@ extern "C" h2_status h2_gmres_solve_batch(h2_handle h, int64_t n_rhs, const void
         r.outer = outer[c];
         r.rel_residual = rel[c];
         r.corrections = S.corrections[c];
+        r.reorth = S.reorth[c];
         all = all && r.converged;
     }
     return all ? H2_OK : H2_NOT_CONVERGED;

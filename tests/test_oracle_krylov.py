@@ -153,3 +153,53 @@ def test_bicgstab_against_scipy_iterations():
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
     # two products per full step, one more for the closing true residual
     assert rep.matvecs <= 2 * rep.iterations + 1
+
+
+# ---------------------------------------------------------------- DGKS reorthogonalisation
+@pytest.mark.parametrize("restart", [50, 5])
+@pytest.mark.parametrize("case", [dict(n=6, side=0.5, seed=3), dict(n=7, side=1.0, seed=4)])
+def test_dgks_matches_cgs2_and_scipy(restart, case):
+    # the selective second pass is the same method as two passes every step: equal
+    # iteration counts, both within one of scipy's GMRES, solutions equal to rounding
+    Z, g = _vie_matrix(**case)
+    b = h2gen.random_vector(Z.shape[0], 12)
+    x1, r1 = krylov.gmres(lambda v: Z @ v, b, tol=1e-8, restart=restart, ortho="dgks")
+    x2, r2 = krylov.gmres(lambda v: Z @ v, b, tol=1e-8, restart=restart, ortho="cgs2")
+    _, its, info = _scipy_iters(Z, b, restart, 1e-8)
+    assert r1.converged and r2.converged and info == 0
+    assert r1.iterations == r2.iterations and abs(r1.iterations - its) <= 1
+    assert r2.reorth == r2.iterations and 0 <= r1.reorth <= r1.iterations
+    assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x2)
+
+
+def test_dgks_second_pass_only_when_the_norm_drops():
+    n = 12
+    # cyclic shift, b = e_0: every A v_j = e_{j+1} is orthogonal to the basis (no second pass)
+    # until the last step, where A v = e_0 lies in the span and the first pass removes all of it
+    S = np.roll(np.eye(n), 1, axis=0).astype(np.complex128)
+    b = np.zeros(n, np.complex128)
+    b[0] = 1.0
+    x, rep = krylov.gmres(lambda v: S @ v, b, tol=1e-12, restart=n)
+    assert rep.converged and rep.iterations == n and rep.reorth == 1
+    # A = I + 0.05 R: each A v_j is mostly v_j, the first pass removes > 1 - 1/sqrt(2) of it
+    rng = np.random.default_rng(2)
+    R = rng.standard_normal((n, n)) / np.sqrt(n)
+    A = (np.eye(n) + 0.05 * R).astype(np.complex128)
+    b = rng.standard_normal(n).astype(np.complex128)
+    x, rep = krylov.gmres(lambda v: A @ v, b, tol=1e-12, restart=n)
+    assert rep.converged and rep.reorth == rep.iterations
+    # the threshold itself: A = [[1, 0], [beta, 2]], b = e_0, so the first step's w = (1, beta)
+    # keeps beta / sqrt(1 + beta^2) of its norm after the first pass; the second (last) step
+    # lies in the span and always takes the second pass
+    for beta, passes in ((1.01, 1), (0.99, 2)):
+        A = np.array([[1.0, 0.0], [beta, 2.0]], np.complex128)
+        x, rep = krylov.gmres(lambda v: A @ v, np.array([1.0, 0.0], np.complex128), tol=1e-14, restart=2)
+        assert rep.iterations == 2 and rep.reorth == passes, (beta, rep.reorth)
+        assert np.linalg.norm(A @ x - [1.0, 0.0]) <= 1e-14
+
+
+def test_dgks_threshold_value():
+    # the test's constant is 1/sqrt(2): a second pass when less than that fraction is left
+    assert krylov.DGKS == pytest.approx(2 ** -0.5, rel=1e-16)
+    with pytest.raises(ValueError):
+        krylov.gmres(lambda v: v, np.ones(3, np.complex128), ortho="mgs")
