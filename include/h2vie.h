@@ -221,6 +221,23 @@ h2_status h2_bicgstab_workspace(h2_handle h, size_t* bytes);
 h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
                             h2_gmres_report* rep, void* work, size_t work_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same solve as h2_bicgstab_solve,
+ * same kernels and same results, with its workspace in a device array of the
+ * library (h2_bicgstab_static_bytes() = 128 MiB, one copy per device, held
+ * until the process ends).  It calls no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating routine (both entry points read their per-step scalars into
+ * pageable host memory).  Limit: the workspace of
+ * h2_bicgstab_workspace must fit in the array (N up to about 1.19 million
+ * unknowns); larger N returns INVALID_ARG.  The handle's device must be current
+ * (INVALID_ARG otherwise).  Every call on one device shares that device's array:
+ * calls that overlap in time on one device (any streams, any handles) race and
+ * must not be made; the solve initialises everything it reads.  b, x, tol,
+ * max_matvec, rep and the stream as for h2_bicgstab_solve; synchronises it. */
+size_t h2_bicgstab_static_bytes(void);
+h2_status h2_bicgstab_solve_static(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
+                                   h2_gmres_report* rep, void* stream);
+
 /* Solve Z x_c = b_c for n_rhs right-hand sides at once (the paper's many
  * right-hand sides, Sec. IV.D): every column runs its own restarted GMRES (FP64
  * Arnoldi with the same selective second Gram-Schmidt pass, per column, Givens,

@@ -103,6 +103,10 @@ def load() -> C.CDLL:
     lib.h2_bicgstab_workspace.argtypes = [vp, C.POINTER(sz)]
     lib.h2_bicgstab_solve.restype = C.c_int
     lib.h2_bicgstab_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int32, C.POINTER(GmresReport), vp, sz, vp]
+    lib.h2_bicgstab_static_bytes.restype = sz
+    lib.h2_bicgstab_static_bytes.argtypes = []
+    lib.h2_bicgstab_solve_static.restype = C.c_int
+    lib.h2_bicgstab_solve_static.argtypes = [vp, vp, vp, C.c_double, C.c_int32, C.POINTER(GmresReport), vp]
     lib.h2_stats.restype = C.c_int
     lib.h2_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.h2_group_plan.restype = C.c_int

@@ -96,20 +96,25 @@ class H2Operator:
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
                               rep.rel_residual, rep.corrections, rep.reorth)
 
-    def bicgstab(self, b, x=None, tol: float = 1e-6, max_matvec: int = 10000, stream=None):
-        """Solve Z x = b by FP64 BiCGStab on the device (x0 = 0)."""
+    def bicgstab(self, b, x=None, tol: float = 1e-6, max_matvec: int = 10000, stream=None, static: bool = False):
+        """Solve Z x = b by FP64 BiCGStab on the device (x0 = 0).  static=True takes the
+        entry point that allocates nothing (workspace in the library's device array)."""
         import torch
         if b.dtype != torch.complex128 or not b.is_cuda or b.shape != (self.N,):
             raise ValueError("b must be a complex128 CUDA tensor of length N")
         if x is None:
             x = torch.empty_like(b)
-        nbytes = C.c_size_t(0)
-        _lib.check(self.lib.h2_bicgstab_workspace(self.handle, C.byref(nbytes)))
-        work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         rep = _lib.GmresReport()
-        st = self.lib.h2_bicgstab_solve(self.handle, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
-                                        int(max_matvec), C.byref(rep), C.c_void_p(work.data_ptr()), nbytes,
-                                        _stream_ptr(stream))
+        if static:
+            st = self.lib.h2_bicgstab_solve_static(self.handle, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                                   float(tol), int(max_matvec), C.byref(rep), _stream_ptr(stream))
+        else:
+            nbytes = C.c_size_t(0)
+            _lib.check(self.lib.h2_bicgstab_workspace(self.handle, C.byref(nbytes)))
+            work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            st = self.lib.h2_bicgstab_solve(self.handle, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                            float(tol), int(max_matvec), C.byref(rep), C.c_void_p(work.data_ptr()),
+                                            nbytes, _stream_ptr(stream))
         _lib.check(st, allow=(_lib.H2_OK, _lib.H2_NOT_CONVERGED))
         return x, GmresResult(bool(rep.converged), rep.iterations, rep.matvecs, rep.restarts, rep.outer,
                               rep.rel_residual)

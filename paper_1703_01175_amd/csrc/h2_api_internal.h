@@ -103,6 +103,7 @@ struct h2_handle_s {
     h2_stats_t stats{};
     char* base = nullptr;
     size_t bytes = 0;
+    int device = -1;                    // device current at build (where base lives)
     void* aux = nullptr;
     size_t aux_bytes = 0;
     int tiers = 1;

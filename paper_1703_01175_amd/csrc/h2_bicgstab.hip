@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 
 #include "h2_api_internal.h"
 
@@ -120,7 +121,7 @@ struct BiSolver {
     int64_t N;
     int nblk;
     BiWork W;
-    double2* host = nullptr;   // pinned, 16 complex
+    double2* host = nullptr;   // 16 complex of host memory
 
     hipError_t dot(const double2* a, const double2* b, int slot) {
         kc_dot<<<nblk, 256, 0, s>>>(a, b, N, W.part);
@@ -153,25 +154,30 @@ extern "C" h2_status h2_bicgstab_workspace(h2_handle h, size_t* bytes) {
     return H2_OK;
 }
 
-extern "C" h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
-                                       h2_gmres_report* rep, void* work, size_t work_bytes, void* stream) {
+namespace {
+
+h2_status check_args(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec, h2_gmres_report* rep) {
     if (!handle_live(h)) return handle_fail(H2_ERR_BAD_HANDLE, "invalid handle");
-    if (!b || !x || !rep || !work) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
+    if (!b || !x || !rep) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
     if (!(tol > 0.0) || max_matvec < 1) return handle_fail(H2_ERR_INVALID_ARG, "tol must be > 0 and max_matvec >= 1");
     if ((reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(x)) % 16)
         return handle_fail(H2_ERR_INVALID_ARG, "b and x must be 16-byte aligned");
+    return H2_OK;
+}
+
+// The solve on a workspace at `base` (256-byte aligned, bi_layout bytes); `host`:
+// 16 complex of host memory for the scalars read back each step.  Allocates nothing.
+h2_status bicgstab_run(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec, h2_gmres_report* rep,
+                       char* base, double2* host, hipStream_t stream) {
     const int64_t N = int64_t(h->dev.n_vox) * kNcomp;
-    if (work_bytes < bi_layout(N, nullptr, nullptr)) return handle_fail(H2_ERR_OOM, "BiCGStab workspace too small");
     BiSolver S{};
     S.d = &h->dev;
     S.lv = &h->lv;
-    S.s = reinterpret_cast<hipStream_t>(stream);
+    S.s = stream;
     S.N = N;
     S.nblk = int(std::min<int64_t>(kBlocks, (N + 255) / 256));
-    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~uintptr_t(255));
     bi_layout(N, &S.W, base);
-    if (hipHostMalloc((void**)&S.host, 16 * sizeof(double2), hipHostMallocDefault) != hipSuccess)
-        return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
+    S.host = host;
     *rep = h2_gmres_report{};
     const double2* B = (const double2*)b;
     double2* X = (double2*)x;
@@ -250,7 +256,70 @@ extern "C" h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, doub
     rep->iterations = its;
     rep->matvecs = mv;
     if (hipStreamSynchronize(S.s) != hipSuccess && st >= 0) st = handle_fail(H2_ERR_DEVICE, "solve synchronisation failed");
-    (void)hipHostFree(S.host);
     if (st < 0) return st;
     return rep->converged ? H2_OK : H2_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" h2_status h2_bicgstab_solve(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
+                                       h2_gmres_report* rep, void* work, size_t work_bytes, void* stream) {
+    h2_status st = check_args(h, b, x, tol, max_matvec, rep);
+    if (st != H2_OK) return st;
+    if (!work) return handle_fail(H2_ERR_INVALID_ARG, "null argument");
+    const int64_t N = int64_t(h->dev.n_vox) * kNcomp;
+    if (work_bytes < bi_layout(N, nullptr, nullptr)) return handle_fail(H2_ERR_OOM, "BiCGStab workspace too small");
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~uintptr_t(255));
+    double2 host[16];                    // scalars read back each step
+    return bicgstab_run(h, b, x, tol, max_matvec, rep, base, host, reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- without allocation
+// The workspace of h2_bicgstab_solve_static lives in this file-scope device array
+// (one copy per device, held until the process ends).  Host code never uses the
+// array's name as a device address: the address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+namespace {
+constexpr size_t kStaticWorkBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticWorkBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current).
+h2_status static_workspace(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return handle_fail(H2_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return handle_fail(H2_ERR_DEVICE, "static workspace address not available");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return H2_OK;
+}
+}  // namespace
+
+extern "C" size_t h2_bicgstab_static_bytes(void) { return kStaticWorkBytes; }
+
+extern "C" h2_status h2_bicgstab_solve_static(h2_handle h, const void* b, void* x, double tol, int32_t max_matvec,
+                                              h2_gmres_report* rep, void* stream) {
+    h2_status st = check_args(h, b, x, tol, max_matvec, rep);
+    if (st != H2_OK) return st;
+    const int64_t N = int64_t(h->dev.n_vox) * kNcomp;
+    const size_t need = bi_layout(N, nullptr, nullptr);
+    if (need > kStaticWorkBytes)
+        return handle_fail(H2_ERR_INVALID_ARG, "N too large for the static BiCGStab workspace (needs more than 128 MiB)");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+        return handle_fail(H2_ERR_INVALID_ARG, "the handle's device must be current");
+    char* base = nullptr;
+    if ((st = static_workspace(cur, &base)) != H2_OK) return st;
+    double2 host[16];                    // scalars read back each step (pageable host memory)
+    return bicgstab_run(h, b, x, tol, max_matvec, rep, base, host, reinterpret_cast<hipStream_t>(stream));
 }

@@ -692,6 +692,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "build synchronisation failed: %s", hipGetErrorString(e));
 
     h2_handle h = new h2_handle_s();
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     DevH2& D = h->dev;
     D.n_vox = int(d->n_vox);
     D.n_clusters = nc;
