@@ -127,6 +127,15 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solves")
     ap.add_argument("--near", choices=("auto", "full"), default="auto",
                     help="near-field mode of the FP64 product: symmetric when available (auto), or every block")
+    ap.add_argument("--couplings", choices=("sym", "full"), default="sym",
+                    help="sym: couplings symmetrised (S_st := S_ts^T) and each unordered pair streamed once; "
+                         "full: the construction's couplings, every ordered block streamed")
+    ap.add_argument("--keep-all-near", action="store_true",
+                    help="headline handle streams every near block (no identical blocks stored once)")
+    ap.add_argument("--no-streamed", action="store_true",
+                    help="skip the leg that streams every near block (both near modes)")
+    ap.add_argument("--solve-rhs", type=int, default=32,
+                    help="right-hand sides of the batched BF16x3 GMRES-IR leg (0: skip)")
     ap.add_argument("--cache", default=None,
                     help="directory holding a saved representation of the workload (built and saved if absent)")
     ap.add_argument("--batched", action="store_true",
@@ -193,6 +202,11 @@ def main():
             log(f"[bench] saved representation to {args.cache}")
     build_s = time.time() - t0
     log(f"[bench] host construction {build_s:.1f}s")
+    if args.couplings == "sym":
+        from h2gen.construct import symmetrize_couplings
+        t0 = time.time()
+        d = symmetrize_couplings(d)
+        log(f"[bench] couplings symmetrised (S_st := S_ts^T) in {time.time() - t0:.1f}s")
     x_np = h2gen.random_vector(3 * g.n_vox, 1)
     b_np = h2gen.plane_wave(g, seed)[0]
 
@@ -202,129 +216,57 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
-    H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0")
+    H = H2Operator(d, tiers=("fp64", "fp32"), device="cuda:0", keep_all_near=args.keep_all_near)
     if args.near == "full":
         H.near_mode(False)
     upload_s = time.time() - t0
-    st = H.stats()
-    log(f"[bench] upload {upload_s:.1f}s, device buffer {st['dev_bytes']/1e9:.2f} GB")
+    log(f"[bench] upload {upload_s:.1f}s, device buffer {H.stats()['dev_bytes']/1e9:.2f} GB")
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
-    for _ in range(args.warmup):
-        H.matvec(x, out=y)
-    torch.cuda.synchronize()
-    # the timed region: products as the library runs them (with stored-once near blocks
-    # the early near passes overlap the couplings on a side stream)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        H.matvec(x, out=y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    # per-kernel-family durations: the same products again with the library's HIP events
-    # around each family (which keeps the families in order on the product's stream)
-    assert H.lib.h2_profile_enable(H.handle, 1) == 0
-    import ctypes as C
-    buf = (C.c_byte * 128)()
-    H.lib.h2_profile_read(H.handle, buf)       # reset
-    for _ in range(args.steps):
-        H.matvec(x, out=y)
-    torch.cuda.synchronize()
-    assert H.lib.h2_profile_read(H.handle, buf) == 0
-    fam_ms = np.frombuffer(bytes(buf)[:64], np.float64).copy()
-    fam_n = np.frombuffer(bytes(buf)[64:], np.int64).copy()
-    H.lib.h2_profile_enable(H.handle, 0)
-    ms_per = total_ms / args.steps
-    sym = H.near_mode()[0]
-    names = ["prologue", "leaf_forward", "upward", "coupling", "downward",
-             "near_sym" if sym else "near_epilogue", "near_sym_finish"]
-    fam = {names[i]: round(float(fam_ms[i] / max(fam_n[i], 1)), 4) for i in range(7) if fam_n[i] > 0}
-    log(f"[bench] {ms_per:.3f} ms per product; per family (ms): {fam}")
-
-    near_ms = fam_ms[5] / max(fam_n[5], 1)
-    # identical near blocks stored once are read through the caches: their HBM bytes
-    # are the stored copies, not the per-pair stream
-    cached = st["near_stored_elems"] < st["near_elems"]
-    if sym:
-        nb, nb_finish = near_sym_bytes(d)
-        product_bytes = st["bytes_fp64"] - 16.0 * d.near.size + nb - 2 * 16.0 * 3 * g.n_vox + nb_finish
-        streamed = near_sym_owned(d)
-    else:
-        nb = near_kernel_bytes(d)
-        product_bytes = st["bytes_fp64"]
-        streamed = float(d.near.size)
-    if cached:
-        # the block stream of the near kernel is served from the caches; HBM reads the stored blocks
-        nb -= 16.0 * (streamed - st["near_stored_elems"])
-        product_bytes -= 16.0 * (streamed - st["near_stored_elems"])
-    near_kernel = "k_near_sym" if sym else "k_near_epilogue"
-    achieved = nb / (near_ms * 1e-3) / 1e9
-    coup_ms = fam_ms[3] / max(fam_n[3], 1)
-    coup_bytes = 16.0 * d.coupling.size + 4.0 * sum(int(r) for r in d.rank[d.far_s])
-    whole_gbs = product_bytes / (ms_per * 1e-3) / 1e9
-    near_flops = 24.0 * d.near.size                       # 3 columns x 8 real flops per near entry
-    if coup_ms > near_ms:
-        roofline = {"bound": "hbm", "kernel": "k_coupling", "achieved": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2),
-                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(coup_bytes / (coup_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                    "traffic": measured_traffic(args.workload, "k_coupling"), "bytes_per_launch": coup_bytes,
-                    "avg_ms": round(float(coup_ms), 4)}
-    elif not cached:
-        roofline = {"bound": "hbm", "kernel": near_kernel, "achieved": round(achieved, 2),
-                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                    "traffic": measured_traffic(args.workload, near_kernel), "bytes_per_launch": nb,
-                    "avg_ms": round(float(near_ms), 4)}
-    else:
-        tf = near_flops / (near_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": near_kernel, "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
-                    "traffic": measured_traffic(args.workload, near_kernel), "flops_per_launch": near_flops,
-                    "avg_ms": round(float(near_ms), 4),
-                    "note": "identical near blocks stored once and read from the caches; FP64 vector peak"}
+    head = product_leg(H, d, x, y, args.steps, args.warmup, args.workload)
     result_gpu = y.cpu().numpy()
     extra = {}
+    if H.coupling_mode()[0]:
+        # the same handle with every ordered coupling block streamed
+        H.coupling_mode(False)
+        extra["coupling_full_mode"] = product_leg(H, d, x, y, args.steps, args.warmup, args.workload)
+        extra["coupling_full_mode"]["max_rel_diff_vs_headline"] = float(
+            np.linalg.norm(y.cpu().numpy() - result_gpu) / np.linalg.norm(result_gpu))
+        H.coupling_mode(True)
     if not args.no_solve:
-        for prec in ("fp64", "fp32"):
-            bt = torch.from_numpy(b_np).to(dev)
-            torch.cuda.synchronize()
-            t0 = time.time()
-            xs, rep = H.gmres(bt, tol=1e-6, restart=50, precision=prec, inner_tol=1e-3)
-            torch.cuda.synchronize()
-            dt = time.time() - t0
-            extra[f"gmres_{prec}"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
-                                          iterations=rep.iterations, matvecs=rep.matvecs, outer=rep.outer,
-                                          converged=rep.converged, rel_residual=rep.rel_residual)
-            log(f"[bench] GMRES {prec}: {dt:.3f}s, {rep.iterations} its, {rep.matvecs} products, "
-                f"residual {rep.rel_residual:.2e}")
-        bt = torch.from_numpy(b_np).to(dev)
-        torch.cuda.synchronize()
+        extra.update(solve_legs(H, b_np, dev))
+    if not args.keep_all_near and not args.no_streamed:
+        # the general case: every near block streamed from HBM (no identical blocks shared)
+        H.close()
+        del H
+        torch.cuda.empty_cache()
         t0 = time.time()
-        xs, rep = H.bicgstab(bt, tol=1e-6)
-        torch.cuda.synchronize()
-        dt = time.time() - t0
-        extra["bicgstab_fp64"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
-                                      iterations=rep.iterations, matvecs=rep.matvecs, converged=rep.converged,
-                                      rel_residual=rep.rel_residual)
-        log(f"[bench] BiCGStab fp64: {dt:.3f}s, {rep.iterations} steps, {rep.matvecs} products, "
-            f"residual {rep.rel_residual:.2e}")
+        Hs = H2Operator(d, tiers=("fp64",), device="cuda:0", keep_all_near=True)
+        log(f"[bench] streamed-near upload {time.time() - t0:.1f}s")
+        streamed = {}
+        for mode in ("symmetric", "full"):
+            Hs.near_mode(mode == "symmetric")
+            streamed[mode] = product_leg(Hs, d, x, y, args.steps, args.warmup, args.workload)
+            ys = y.cpu().numpy()
+            streamed[mode]["max_rel_diff_vs_headline"] = float(np.linalg.norm(ys - result_gpu) /
+                                                               np.linalg.norm(result_gpu))
+        extra["streamed_near"] = streamed
+        Hs.close()
+        del Hs
+        torch.cuda.empty_cache()
+    else:
+        H.close()
+        del H
+        torch.cuda.empty_cache()
+    if args.solve_rhs > 0 and not args.no_solve:
+        extra["batched_solve"] = batched_solve_leg(d, g, args.solve_rhs, dev)
 
     cpu = None
     parity = None
     if not args.no_cpu:
-        from oracle import matvec as om
-        t0 = time.time()
-        yo = om.h2_matvec(d, x_np)
-        cpu_s = time.time() - t0
-        parity = float(np.linalg.norm(result_gpu - yo) / np.linalg.norm(yo))
-        log(f"[bench] oracle product {cpu_s:.1f}s on the host, GPU vs oracle rel err {parity:.2e}")
-        cpu = {"value": round(1.0 / cpu_s, 6), "unit": "matvec/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full oracle FP64 product on the same {args.workload} representation "
-                         f"(N={3 * g.n_vox}), single Python thread",
-               "seconds": round(cpu_s, 3), "host_cpus": len(os.sched_getaffinity(0))}
+        cpu, parity = cpu_baseline(d, x_np, result_gpu, args.workload, g)
 
+    ms_per = head["ms_per_step"]
     out = {
         "metric": "H^2 matvec/s (FP64, 3 field components) + HBM GB/s",
         "value": round(1000.0 / ms_per, 4),
@@ -340,20 +282,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {edge}^3 voxels, {side} wavelengths per side, "
                                f"eps_r {eps_r}, seed {seed}, leaf 64, eta 1, eps {eps}",
-                   "N": 3 * g.n_vox, "n_rhs": 1, "precision": "fp64"},
-        "hbm_gbs_whole_product": round(whole_gbs, 2),
-        "algorithmic_bytes_per_product": product_bytes,
-        "near_mode": "symmetric" if sym else "full",
-        "roofline": roofline,
-        "near_kernel": {"kernel": near_kernel, "avg_ms": round(float(near_ms), 4), "hbm_bytes": nb,
-                        "achieved_gbs": round(achieved, 2),
-                        "fp64_tflops": round(near_flops / (near_ms * 1e-3) / 1e12, 3)},
-        "near_storage": {"stored_once": bool(cached), "unique_blocks": int(st["near_unique"]),
-                         "near_pairs": int(st["n_near"]), "stored_elems": int(st["near_stored_elems"]),
-                         "elems": int(st["near_elems"])},
-        "coupling_kernel": {"avg_ms": round(float(coup_ms), 4),
-                            "achieved_gbs": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2) if coup_ms > 0 else None},
-        "kernel_ms": fam,
+                   "N": 3 * g.n_vox, "n_rhs": 1, "precision": "fp64",
+                   "near_storage": "every block streamed" if args.keep_all_near else
+                   "identical near blocks stored once",
+                   "couplings": "symmetrised, each unordered pair streamed once" if args.couplings == "sym" else
+                   "as constructed (eq. (18)), every ordered block streamed"},
+        "roofline": head["roofline"],
+        "roofline_whole_product": head["roofline_whole_product"],
+        "near_mode": head["near_mode"],
+        "coupling_mode": head["coupling_mode"],
+        "coupling_kernel": head["coupling_kernel"],
+        "near_kernel": head["near_kernel"],
+        "near_storage": head["near_storage"],
+        "kernel_ms_per_product": head["kernel_ms"],
         "cpu_baseline": cpu,
         "parity_rel_err_vs_oracle": parity,
         "host_build_s": round(build_s, 2),
@@ -361,6 +302,277 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def product_leg(H, d, x, y, steps, warmup, workload):
+    """Time `steps` FP64 products y = Z x on handle H.  The library brackets every kernel
+    family with HIP events on the stream it runs on, inside the timed region, so the
+    per-kernel durations are those of the products timed (near passes overlapping the
+    couplings on the side stream included)."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    st = H.stats()
+    assert H.lib.h2_profile_enable(H.handle, 1) == 0
+    buf = (C.c_byte * 128)()
+    for _ in range(warmup):
+        H.matvec(x, out=y)
+    torch.cuda.synchronize()
+    H.lib.h2_profile_read(H.handle, buf)           # reset (and pool the warm-up's events)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        H.matvec(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    assert H.lib.h2_profile_read(H.handle, buf) == 0
+    fam_ms = np.frombuffer(bytes(buf)[:64], np.float64).copy()
+    fam_n = np.frombuffer(bytes(buf)[64:], np.int64).copy()
+    H.lib.h2_profile_enable(H.handle, 0)
+    ms_per = total_ms / steps
+    sym = H.near_mode()[0]
+    names = ["prologue", "leaf_forward", "upward", "coupling", "downward",
+             "near_sym" if sym else "near_epilogue", "near_sym_finish", "coupling_recv"]
+    fam = {names[i]: round(float(fam_ms[i] / steps), 4) for i in range(8) if fam_n[i] > 0}
+    log(f"[bench] {ms_per:.3f} ms per product ({'symmetric' if sym else 'full'} near mode); "
+        f"per family (ms per product): {fam}")
+
+    near_ms = fam_ms[5] / steps
+    # identical near blocks stored once are read through the caches: their HBM bytes
+    # are the stored copies, not the per-pair stream
+    cached = st["near_stored_elems"] < st["near_elems"]
+    n_vox = int(d.n_vox)
+    if sym:
+        nb, nb_finish = near_sym_bytes(d)
+        product_bytes = st["bytes_fp64"] - 16.0 * d.near.size + nb - 2 * 16.0 * 3 * n_vox + nb_finish
+        streamed = near_sym_owned(d)
+    else:
+        nb = near_kernel_bytes(d)
+        nb_finish = 0.0
+        product_bytes = st["bytes_fp64"]
+        streamed = float(d.near.size)
+    if cached:
+        # the block stream of the near kernel is served from the caches; HBM reads the stored blocks
+        nb -= 16.0 * (streamed - st["near_stored_elems"])
+        product_bytes -= 16.0 * (streamed - st["near_stored_elems"])
+    near_kernel = "k_near_sym" if sym else "k_near_epilogue"
+    near_launches = 1 if sym else int(st["near_passes"])       # near-kernel dispatches per product
+    coup_ms = fam_ms[3] / steps
+    coup_sym = H.coupling_mode()[0]
+    if coup_sym:
+        # owned blocks streamed once, their gather indices, one 3-column partial
+        # written per owned column (k_coupling_sym); partials read back and the receiving
+        # coefficient rows read and written (k_coupling_recv)
+        oc = float(st["coupling_owned_cols"])
+        coup_bytes = 16.0 * st["coupling_owned_elems"] + 4.0 * oc + 48.0 * oc
+        recv_bytes = 48.0 * oc + 2 * 48.0 * st["coef_rows"]
+        product_bytes += coup_bytes + recv_bytes - 16.0 * d.coupling.size
+    else:
+        coup_bytes = 16.0 * d.coupling.size + 4.0 * float(d.rank[d.far_s].sum())
+        recv_bytes = 0.0
+        product_bytes += 4.0 * float(d.rank[d.far_s].sum())
+    coup_kernel = "k_coupling_sym" if coup_sym else "k_coupling"
+    near_flops = 24.0 * d.near.size                       # 3 columns x 8 real flops per near entry
+    # each family at its own bound: couplings and streamed near blocks at HBM speed, near
+    # blocks held in the caches at the FP64 vector peak; the rest (under 0.1 GB) at HBM speed
+    small_bytes = product_bytes - coup_bytes - recv_bytes - nb - nb_finish
+    if cached:
+        near_roof_ms = near_flops / (PEAK_FP64_TFLOPS * 1e12) * 1e3
+    else:
+        near_roof_ms = (nb + nb_finish) / (PEAK_HBM_GBS * 1e9) * 1e3
+    roof_ms = (coup_bytes + recv_bytes + max(small_bytes, 0.0)) / (PEAK_HBM_GBS * 1e9) * 1e3 + near_roof_ms
+    whole = {"bytes": product_bytes, "ms": round(ms_per, 4),
+             "achieved": round(product_bytes / (ms_per * 1e-3) / 1e9, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": round(product_bytes / (ms_per * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+             "roofline_ms": round(roof_ms, 4), "frac_of_roofline_time": round(roof_ms / ms_per, 4),
+             "note": "algorithmic bytes of the whole product over its measured time; roofline_ms sums each "
+                     "kernel family at its own bound (HBM, or the FP64 vector peak for near blocks held in "
+                     "the caches)"}
+    near_avg_launch_ms = near_ms / max(near_launches, 1)
+    if coup_ms >= near_ms:
+        roofline = {"bound": "hbm", "kernel": coup_kernel, "achieved": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(coup_bytes / (coup_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                    "traffic": measured_traffic(workload, coup_kernel), "bytes_per_launch": coup_bytes,
+                    "avg_ms": round(float(coup_ms), 4), "launches_per_product": 1}
+    elif not cached:
+        achieved = nb / (near_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": near_kernel, "achieved": round(achieved, 2),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": measured_traffic(workload, near_kernel), "bytes_per_launch": nb,
+                    "avg_ms": round(float(near_ms), 4), "launches_per_product": 1}
+    else:
+        tf = near_flops / (near_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": near_kernel, "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                    "traffic": measured_traffic(workload, near_kernel),
+                    "flops_per_launch": near_flops / max(near_launches, 1),
+                    "avg_ms": round(float(near_avg_launch_ms), 4), "launches_per_product": near_launches,
+                    "note": "identical near blocks stored once and read from the caches; FP64 vector peak"}
+    return {
+        "ms_per_step": ms_per,
+        "matvec_per_s": round(1000.0 / ms_per, 3),
+        "roofline": roofline,
+        "roofline_whole_product": whole,
+        "near_mode": "symmetric" if sym else "full",
+        "near_kernel": {"kernel": near_kernel, "ms_per_product": round(float(near_ms), 4),
+                        "launches_per_product": near_launches, "hbm_bytes": nb,
+                        "achieved_gbs": round(nb / (near_ms * 1e-3) / 1e9, 2),
+                        "fp64_tflops": round(near_flops / (near_ms * 1e-3) / 1e12, 3)},
+        "coupling_mode": "symmetric" if coup_sym else "full",
+        "coupling_kernel": {"kernel": coup_kernel, "ms_per_product": round(float(coup_ms), 4), "bytes": coup_bytes,
+                            "achieved_gbs": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2) if coup_ms > 0 else None,
+                            "recv_ms_per_product": round(float(fam_ms[7] / steps), 4) if coup_sym else None,
+                            "recv_bytes": recv_bytes if coup_sym else None},
+        "near_storage": {"stored_once": bool(cached), "unique_blocks": int(st["near_unique"]),
+                         "near_pairs": int(st["n_near"]), "stored_elems": int(st["near_stored_elems"]),
+                         "elems": int(st["near_elems"])},
+        "kernel_ms": fam,
+    }
+
+
+def solve_legs(H, b_np, dev):
+    """One GMRES(50) solve to 1e-6 per storage tier (plain FP64, FP32 refinement) and one
+    FP64 BiCGStab solve, on the headline handle."""
+    import torch
+    extra = {}
+    bt = torch.from_numpy(b_np).to(dev)
+    for prec in ("fp64", "fp32"):            # warm-up: loads the solvers' code and sizes the caches
+        H.gmres(bt, tol=1e-6, restart=50, precision=prec, inner_tol=1e-3, max_matvec=3)
+    H.bicgstab(bt, tol=1e-6, max_matvec=2)
+    for prec in ("fp64", "fp32"):
+        bt = torch.from_numpy(b_np).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, rep = H.gmres(bt, tol=1e-6, restart=50, precision=prec, inner_tol=1e-3)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        extra[f"gmres_{prec}"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
+                                      iterations=rep.iterations, matvecs=rep.matvecs, outer=rep.outer,
+                                      converged=rep.converged, rel_residual=rep.rel_residual)
+        log(f"[bench] GMRES {prec}: {dt:.3f}s, {rep.iterations} its, {rep.matvecs} products, "
+            f"residual {rep.rel_residual:.2e}")
+    bt = torch.from_numpy(b_np).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    xs, rep = H.bicgstab(bt, tol=1e-6)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    extra["bicgstab_fp64"] = dict(seconds=round(dt, 4), solves_per_s=round(1.0 / dt, 4),
+                                  iterations=rep.iterations, matvecs=rep.matvecs, converged=rep.converged,
+                                  rel_residual=rep.rel_residual)
+    log(f"[bench] BiCGStab fp64: {dt:.3f}s, {rep.iterations} steps, {rep.matvecs} products, "
+        f"residual {rep.rel_residual:.2e}")
+    return extra
+
+
+def batched_solve_leg(d, g, n, dev):
+    """Solves per second per right-hand side to a 1e-6 FP64 residual: n seeded plane waves
+    (seed 100) by batched GMRES(30) iterative refinement on the BF16x3 product (FP64
+    Arnoldi, FP64 outer residual), against plain FP64 GMRES(50) one right-hand side at a
+    time (the first two).  Every column's true residual is taken with the FP64 product."""
+    import torch
+    import h2gen
+    from paper_1703_01175_amd import H2Operator
+    t0 = time.time()
+    H = H2Operator(d, tiers=("fp64", "bf16x3"), max_rhs=n, device="cuda:0")
+    upload_s = time.time() - t0
+    log(f"[bench] batched-solve handle ({n} right-hand sides, BF16x3 tier) built in {upload_s:.1f}s")
+    B = torch.from_numpy(h2gen.plane_wave(g, 100, count=n)).to(dev)
+    sync = torch.cuda.synchronize
+    H.gmres(B[0], tol=1e-6, restart=50, max_matvec=60)                     # warm-up
+    H.gmres_batch(B, tol=1e-6, restart=30, precision="bf16x3", inner_tol=1e-3, max_matvec=40)
+    sync()
+    log("[bench] batched-solve warm-up done")
+    k = min(2, n)
+    t0 = time.time()
+    single = [H.gmres(B[c], tol=1e-6, restart=50, max_matvec=2000) for c in range(k)]
+    sync()
+    fp64_ms = (time.time() - t0) / k * 1e3
+    log(f"[bench] FP64 GMRES(50), one right-hand side at a time: {fp64_ms:.1f} ms per RHS")
+    t0 = time.time()
+    X, reps = H.gmres_batch(B, tol=1e-6, restart=30, precision="bf16x3", inner_tol=1e-3, max_matvec=2000)
+    sync()
+    batch_ms = (time.time() - t0) / n * 1e3
+    worst = 0.0
+    for c in range(n):
+        r = B[c] - H.matvec(X[c].contiguous())
+        worst = max(worst, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(B[c])))
+    ok = all(r.converged for r in reps) and worst <= 1e-6
+    log(f"[bench] batched BF16x3 GMRES-IR x {n}: {batch_ms:.1f} ms per RHS (FP64 GMRES {fp64_ms:.1f} ms), "
+        f"worst true residual {worst:.2e}")
+    H.close()
+    del H
+    torch.cuda.empty_cache()
+    return {"metric": "GMRES solves/s/RHS to 1e-6 (FP64 true residual)", "rhs": n,
+            "bf16x3_batched_gmres_ir": {"solves_per_s_per_rhs": round(1000.0 / batch_ms, 3),
+                                        "ms_per_rhs": round(batch_ms, 2), "restart": 30, "inner_tol": 1e-3,
+                                        "iterations_max": max(r.iterations for r in reps),
+                                        "outer_max": max(r.outer for r in reps),
+                                        "worst_true_rel_residual_fp64": worst, "all_converged": ok},
+            "fp64_gmres_single": {"solves_per_s_per_rhs": round(1000.0 / fp64_ms, 3), "ms_per_rhs": round(fp64_ms, 2),
+                                  "rhs_timed": k, "iterations": [r.iterations for _, r in single]},
+            "speedup_per_rhs": round(fp64_ms / batch_ms, 3), "upload_s": round(upload_s, 2)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(d, x_np, result_gpu, workload, g):
+    """The oracle's FP64 product (plain NumPy, complex128) timed on the host: one product
+    first (also the parity check against the GPU result), then the median of three with
+    BLAS limited to one thread and the median of two with BLAS on every host core.  cores is
+    the single-thread run's; the all-core run reports its process CPU time over wall time
+    (the oracle's small block products barely thread)."""
+    import numpy as np
+    from oracle import matvec as om
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:                                  # pragma: no cover
+        threadpool_limits = None
+    ncpu = len(os.sched_getaffinity(0))
+
+    def timed(k, threads):
+        ts, cpu_ratio = [], []
+        for _ in range(k):
+            c0, t0 = time.process_time(), time.perf_counter()
+            if threadpool_limits is not None:
+                with threadpool_limits(limits=threads):
+                    om.h2_matvec(d, x_np)
+            else:
+                om.h2_matvec(d, x_np)
+            w = time.perf_counter() - t0
+            ts.append(w)
+            cpu_ratio.append((time.process_time() - c0) / w)
+        return float(np.median(ts)), ts, float(np.median(cpu_ratio))
+
+    t0 = time.perf_counter()
+    yo = om.h2_matvec(d, x_np)
+    first_s = time.perf_counter() - t0
+    parity = float(np.linalg.norm(result_gpu - yo) / np.linalg.norm(yo))
+    log(f"[bench] oracle product {first_s:.1f}s on the host, GPU vs oracle rel err {parity:.2e}")
+    med1, ts1, r1 = timed(3, 1)
+    medn, tsn, rn = timed(2, ncpu)
+    log(f"[bench] oracle product: median {med1:.2f}s with one BLAS thread, {medn:.2f}s with {ncpu}")
+    cpu = {"value": round(1.0 / med1, 6), "unit": "matvec/s", "cores": 1, "kind": "oracle",
+           "sample": f"full oracle FP64 products on the same {workload} representation (N={3 * g.n_vox}): "
+                     f"median of 3 after one warm-up product, BLAS limited to one thread",
+           "seconds_median": round(med1, 3), "seconds": [round(t, 3) for t in ts1],
+           "cpu_over_wall": round(r1, 2), "host_cpus": ncpu, "cpu_model": cpu_model(),
+           "all_cores": {"value": round(1.0 / medn, 6), "unit": "matvec/s", "blas_threads": ncpu,
+                         "seconds_median": round(medn, 3), "seconds": [round(t, 3) for t in tsn],
+                         "cpu_over_wall": round(rn, 2)}}
+    return cpu, parity
 
 
 def batched(args):

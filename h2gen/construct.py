@@ -459,3 +459,54 @@ def build_h2(geom: Geometry, leaf_size: int = 64, eta: float = 1.0, eps: float =
                   near_t=near_t.copy(), near_s=near_s.copy(), near_off=near_off, near=near,
                   chi=geom.chi.copy(), k=float(geom.k), volume=float(geom.volume), sigma=float(geom.sigma),
                   meta=meta)
+
+
+def symmetrize_couplings(d: H2Desc, chunk: int = 1 << 16) -> H2Desc:
+    """Return d with S_ts := (S_ts + S_st^T) / 2 and S_st := S_ts^T for every
+    unordered admissible pair {t, s}.
+
+    G is complex symmetric (its entries depend on |r - r'| only) and the product
+    uses one basis per cluster for rows and columns (G^{t,s} ~ V_t S_ts V_s^T,
+    eq. (8)), so S_st and S_ts^T approximate the same block; eq. (18) computes them
+    from two different Stage I factorisations, and they agree to the truncation
+    accuracy only.  The average keeps that accuracy and makes the stored pair exact
+    transposes bit for bit, so a product may stream each unordered pair once.  The
+    partition lists both orders of every admissible pair (eq. (4) is symmetric in
+    t and s).  Everything else is shared with d; the coupling array is a new copy.
+    """
+    import dataclasses
+    ncl = int(d.level.shape[0])
+    far_t = d.far_t.astype(np.int64)
+    far_s = d.far_s.astype(np.int64)
+    key = far_t * ncl + far_s
+    order = np.argsort(key, kind="stable")
+    pos = np.searchsorted(key[order], far_s * ncl + far_t)
+    if np.any(pos >= key.size):
+        raise ValueError("far list is not symmetric")
+    rev = order[pos]
+    if not np.array_equal(key[rev], far_s * ncl + far_t):
+        raise ValueError("far list is not symmetric")
+    C = d.coupling.copy()
+    rank = d.rank.astype(np.int64)
+    kt, ks = rank[far_t], rank[far_s]
+    first = np.nonzero(far_t < far_s)[0]
+    pairs = np.stack([kt[first], ks[first]], 1)
+    for a, b in np.unique(pairs, axis=0):
+        idx = first[(pairs[:, 0] == a) & (pairs[:, 1] == b)]
+        n_el = int(a * b)
+        if n_el == 0:
+            continue
+        ar = np.arange(n_el, dtype=np.int64)
+        for lo in range(0, idx.size, chunk):
+            i = idx[lo:lo + chunk]
+            j = rev[i]
+            oi = d.far_off[i][:, None] + ar
+            oj = d.far_off[j][:, None] + ar
+            S_ts = C[oi].reshape(-1, b, a)            # [n, col, row] of the k_t x k_s block (column major)
+            S_st = C[oj].reshape(-1, a, b)            # [n, col, row] of the k_s x k_t block
+            M = (S_ts + S_st.transpose(0, 2, 1)) * 0.5
+            C[oi] = M.reshape(-1, n_el)
+            C[oj] = M.transpose(0, 2, 1).reshape(-1, n_el)
+    meta = dict(d.meta)
+    meta["symmetric_couplings"] = True
+    return dataclasses.replace(d, coupling=C, meta=meta)

@@ -147,9 +147,11 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
  * column major N x n_rhs, leading dimension ld (complex elements), in the
  * precision's vector type (FP64: complex double; FP32 and BF16X3: complex
  * float).  The block storage precision is p; accumulation is FP32 for FP32
- * and BF16X3, FP64 otherwise.  x and y must not overlap.
- * Errors: BAD_HANDLE, INVALID_ARG (n_rhs > max_rhs, ld < N, null, tier not
- * built), DEVICE. */
+ * and BF16X3, FP64 otherwise.  x and y must not overlap.  FP64 and FP32 take
+ * any n_rhs (in passes of four right-hand sides when the handle was built with
+ * max_rhs >= 2, else one at a time); BF16X3 takes at most max_rhs.
+ * Errors: BAD_HANDLE, INVALID_ARG (BF16X3 with n_rhs > max_rhs, ld < N, null,
+ * tier not built), DEVICE. */
 h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* y, int64_t n_rhs,
                     int64_t ld, void* stream);
 
@@ -266,6 +268,11 @@ typedef struct {
     int64_t near_stored_elems;     /* complex entries of the near blocks held on the device
                                       (near_elems unless identical blocks are stored once) */
     int64_t near_unique;           /* distinct near blocks held */
+    int64_t near_passes;           /* near-field launches of one full-mode product (1, or several
+                                      passes over the distinct blocks when they are stored once) */
+    int64_t coupling_owned_elems;  /* coupling entries streamed per product in the symmetric
+                                      coupling mode (0: mode not available) */
+    int64_t coupling_owned_cols;   /* their columns (one partial of 3 complex each) */
 } h2_stats_t;
 
 h2_status h2_stats(h2_handle h, h2_stats_t* out);
@@ -347,6 +354,7 @@ enum {
                                near mode the near field alone (own rows and the partials
                                of the other leaf of each streamed pair) */
     H2_K_NEAR_FINISH = 6,   /* symmetric near mode: partials + leaf backward + epilogue */
+    H2_K_COUPLING_RECV = 7, /* symmetric coupling mode: partials S_ts^T X_t added to Y_s */
     H2_K_FAMILIES = 8
 };
 
@@ -374,10 +382,29 @@ typedef struct {
  * mode is not available. */
 h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);
 
+/* Coupling mode of the FP64 and FP32 single-vector products.  G is symmetric and
+ * the product uses one basis per cluster for rows and columns, so a description
+ * whose couplings satisfy S_st = S_ts^T bit for bit (h2gen's symmetrised
+ * couplings; checked at build for every admissible pair, ranks up to 64) lets
+ * the library stream each unordered pair once: the owning cluster adds
+ * S_ts X_s to its coefficients and writes S_ts^T X_t for the other, which adds
+ * those partials before the backward transformation.  This halves the coupling
+ * stream; results agree with the full mode to rounding.
+ *   set: -1 query only, 0 every ordered block, 1 the symmetric mode
+ *   *mode, *available: as for h2_near_mode (either may be NULL).
+ * Handles start in the symmetric mode when it is available.  The multi-RHS
+ * products and the BF16x3 tier stream every block.
+ * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 when the
+ * mode is not available. */
+h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);
+
 /* Diagnostics: with enable = 1, later products on h bracket every kernel
- * family with HIP events on the product's stream; h2_profile_read waits for
- * those events, returns the summed times since the last read, and resets
- * them.  enable = 0 stops recording.  Errors: BAD_HANDLE, INVALID_ARG, DEVICE. */
+ * family with HIP events on the stream it runs on (the product's stream, or the
+ * handle's side stream for the early near-field passes, which keep running
+ * beside the couplings: a family can then count two intervals per product);
+ * h2_profile_read waits for those events, returns the summed times since the
+ * last read, and resets them.  enable = 0 stops recording.  Errors: BAD_HANDLE,
+ * INVALID_ARG, DEVICE. */
 h2_status h2_profile_enable(h2_handle h, int enable);
 h2_status h2_profile_read(h2_handle h, h2_kernel_times* out);
 

@@ -220,6 +220,13 @@ class H2Operator:
                                          C.byref(mode), C.byref(avail)))
         return bool(mode.value), bool(avail.value)
 
+    def coupling_mode(self, symmetric: bool | None = None) -> tuple[bool, bool]:
+        """(symmetric coupling mode in use, available); symmetric=True/False selects it."""
+        mode, avail = C.c_int32(0), C.c_int32(0)
+        _lib.check(self.lib.h2_coupling_mode(self.handle, -1 if symmetric is None else int(bool(symmetric)),
+                                             C.byref(mode), C.byref(avail)))
+        return bool(mode.value), bool(avail.value)
+
     def stats(self) -> dict:
         s = _lib.Stats()
         _lib.check(self.lib.h2_stats(self.handle, C.byref(s)))

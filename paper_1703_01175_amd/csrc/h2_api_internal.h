@@ -41,8 +41,10 @@ bool handle_live(h2_handle h);
 h2_status handle_fail(h2_status st, const char* msg);
 
 // Batched BF16x3 tier (h2_batch_api.cpp)
-// near_off: offset of each near pair's block in the stored FP64 near array
-h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, BatchHost& B);
+// near_off / coup_off: offset of each near / far pair's block in the FP64 arrays as held
+// on the device (coup_off null: the description's offsets)
+h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, const int64_t* coup_off,
+                     BatchHost& B);
 size_t group_need(const h2_handle* hs, int n);
 size_t group_need_batch(BatchHost* B);
 h2_status group_create(const h2_handle* hs, int n, void* mem, size_t bytes, hipStream_t s, h2_group* out);

@@ -22,7 +22,8 @@ namespace h2 {
 static inline int pad16(int v) { return (v + 15) & ~15; }
 
 // ---------------------------------------------------------------- plan of one representation
-h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, BatchHost& B) {
+h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off, const int64_t* coup_off,
+                     BatchHost& B) {
     const int nc = d->n_clusters;
     for (int c = 0; c < nc; ++c)
         if (d->rank[c] > 64) return H2_ERR_BAD_DESC;      // row blocks of the block GEMM hold <= 64 rows
@@ -118,7 +119,7 @@ h2_status plan_batch(const h2_host_desc* d, int max_rhs, const int64_t* near_off
             RelOwner o{1, crow[t], pad16(d->rank[t]), int(B.coup.terms.size()), 0, 0};
             for (int64_t i = ffirst[t]; ffirst[t] >= 0 && i < ffirst[t] + fcount[t]; ++i) {
                 const int s = d->far_s[i];
-                const int64_t a = add_job(1, d->far_off[i], d->rank[t], d->rank[s], d->rank[t], 0);
+                const int64_t a = add_job(1, coup_off ? coup_off[i] : d->far_off[i], d->rank[t], d->rank[s], d->rank[t], 0);
                 B.coup.terms.push_back({a, 1, crow[s], pad16(d->rank[s])});
                 o.nt++;
             }

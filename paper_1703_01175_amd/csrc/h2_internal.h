@@ -76,6 +76,16 @@ struct DevH2 {
     const int* row_colptr = nullptr;    // first entry in colsrc
     const int* colsrc = nullptr;        // coefficient row of each grouped column
 
+    // symmetric couplings (S_st = S_ts^T for every pair): each unordered pair streamed
+    // once by its owner, which also writes S_ts^T X_t for the other cluster
+    bool coup_sym_ok = false;           // the description's couplings allow it
+    bool coup_sym = false;              // single-vector FP64 / FP32 products use it
+    const int* row_nown = nullptr;      // per row slot: owned columns (stored first in the row)
+    const int* row_pbase = nullptr;     // per row slot: its first partial column
+    const int* crecv_ptr = nullptr;     // [n_rowcl + 1] into crecv_p
+    const int* crecv_p = nullptr;       // partial column of the first column of each received block
+    void* cpart = nullptr;              // [owned columns][3] partials S_ts^T X_t (vector type)
+
     // per-level lists for the upward / downward passes
     const int* up_list = nullptr;       // parents with rank > 0, grouped by level (deepest first)
     const int* down_list = nullptr;     // children with a transfer, grouped by level (top first)

@@ -8,6 +8,11 @@
 //   Givens update of the Hessenberg column and of the residual estimate |g_{j+1}|.
 // A cycle ends at m steps, on breakdown, or when the estimate reaches the
 // tolerance; then y = R^-1 g, x += V y, and the true residual b - Z x decides.
+// The second-pass test and the stopping test are taken on the device (per-solve
+// flags gate the kernels of later steps), and the host reads each step's record
+// one step late: it has already queued the next step, so the device never waits
+// for the host inside a cycle.  A step queued after the one that ended the cycle
+// does no Arnoldi work; only its product is spent.
 // With a lower-precision product the solve is iterative refinement: an FP64
 // outer residual and an inner GMRES (FP64 Arnoldi) on the FP32 / BF16 blocks.
 #include <hip/hip_runtime.h>
@@ -38,18 +43,32 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partial[blk][i] = sum over this block's elements of conj(V_i[n]) w[n], i in [i0, i0 + 16)
+// Per-solve device flags: [0] the cycle has stopped (set by k_givens_step), [1] this
+// step needs the second Gram-Schmidt pass, [2] steps that took it.  A kernel given
+// flags runs only while the cycle goes on (and, for the second pass, when needed).
+__device__ __forceinline__ bool gate_open(const int* flags, int second) {
+    return !flags || (flags[0] == 0 && (!second || flags[1] != 0));
+}
+
+// partial[blk][i] = sum over this block's elements of conj(V_i[n]) w[n], i in [i0, i0 + 16);
+// with nrm_partial, the y = 0 blocks also leave their share of ||w||^2 there
 __global__ __launch_bounds__(256) void k_multidot(const double2* __restrict__ V, int64_t ldv, int nvec,
                                                   const double2* __restrict__ w, int64_t N,
-                                                  double2* __restrict__ partial) {
+                                                  double2* __restrict__ partial, double* __restrict__ nrm_partial,
+                                                  const int* __restrict__ flags, int second) {
+    if (!gate_open(flags, second)) return;
     __shared__ double2 red[4][kDotTile];
+    __shared__ double nred[4];
     const int i0 = blockIdx.y * kDotTile;
     const int cnt = min(kDotTile, nvec - i0);
+    const bool with_norm = nrm_partial && blockIdx.y == 0;
     double2 acc[kDotTile];
+    double nn = 0;
 #pragma unroll
     for (int q = 0; q < kDotTile; ++q) acc[q] = make_double2(0, 0);
     for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
         const double2 wv = w[n];
+        nn += wv.x * wv.x + wv.y * wv.y;
 #pragma unroll
         for (int q = 0; q < kDotTile; ++q)
             if (q < cnt) {
@@ -65,6 +84,10 @@ __global__ __launch_bounds__(256) void k_multidot(const double2* __restrict__ V,
         double ry = wave_sum<64>(acc[q].y);
         if (lane == 0) red[wv][q] = make_double2(rx, ry);
     }
+    if (with_norm) {
+        nn = wave_sum<64>(nn);
+        if (lane == 0) nred[wv] = nn;
+    }
     __syncthreads();
     if (threadIdx.x < cnt) {
         const int q = threadIdx.x;
@@ -72,24 +95,55 @@ __global__ __launch_bounds__(256) void k_multidot(const double2* __restrict__ V,
         for (int k = 1; k < 4; ++k) { s.x += red[k][q].x; s.y += red[k][q].y; }
         partial[(int64_t)blockIdx.x * 128 + i0 + q] = s;
     }
+    if (with_norm && threadIdx.x == 0) nrm_partial[blockIdx.x] = nred[0] + nred[1] + nred[2] + nred[3];
 }
 
-// out[i] (+)= sum_blk partial[blk][i]
-__global__ void k_reduce_partial(const double2* __restrict__ partial, int nblk, int nvec, double2* __restrict__ out,
-                                 int accumulate) {
-    const int i = threadIdx.x;
-    if (i >= nvec) return;
-    double2 s = make_double2(0, 0);
-    for (int b = 0; b < nblk; ++b) { s.x += partial[(int64_t)b * 128 + i].x; s.y += partial[(int64_t)b * 128 + i].y; }
-    if (accumulate) { s.x += out[i].x; s.y += out[i].y; }
-    out[i] = s;
+// Block i < nvec: out[i] (+)= sum over blk of partial[blk][i]; block nvec (when
+// nrm_partial): scal[nrm_slot] = sqrt(sum of nrm_partial).  Fixed summation order.
+__global__ __launch_bounds__(256) void k_reduce_dots(const double2* __restrict__ partial, int nblk, int nvec,
+                                                     double2* __restrict__ out, int accumulate,
+                                                     const double* __restrict__ nrm_partial, double* __restrict__ scal,
+                                                     int nrm_slot, const int* __restrict__ flags, int second) {
+    if (!gate_open(flags, second)) return;
+    __shared__ double red[2][4];
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double sx = 0, sy = 0;
+    if (i < nvec) {
+        for (int b = threadIdx.x; b < nblk; b += 256) {
+            const double2 p = partial[(int64_t)b * 128 + i];
+            sx += p.x;
+            sy += p.y;
+        }
+    } else {
+        for (int b = threadIdx.x; b < nblk; b += 256) sx += nrm_partial[b];
+    }
+    sx = wave_sum<64>(sx);
+    sy = wave_sum<64>(sy);
+    if (lane == 0) {
+        red[0][wv] = sx;
+        red[1][wv] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    sx = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    sy = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (i < nvec) {
+        if (accumulate) { sx += out[i].x; sy += out[i].y; }
+        out[i] = make_double2(sx, sy);
+    } else {
+        scal[nrm_slot] = sqrt(sx);
+    }
 }
+
 
 // w[n] += sign * sum_i V_i[n] c_i  (sign = -1: orthogonalise; +1: x += V y)
 // optional: partial squared norms of the result (nrm_partial[blockIdx.x])
 __global__ __launch_bounds__(256) void k_multiaxpy(const double2* __restrict__ V, int64_t ldv, int nvec,
                                                    const double2* __restrict__ c, double sign, double2* __restrict__ w,
-                                                   int64_t N, double* __restrict__ nrm_partial) {
+                                                   int64_t N, double* __restrict__ nrm_partial,
+                                                   const int* __restrict__ flags = nullptr, int second = 0) {
+    if (!gate_open(flags, second)) return;
     __shared__ double2 cs[128];
     __shared__ double red[4];
     for (int i = threadIdx.x; i < nvec; i += 256) cs[i] = c[i];
@@ -157,9 +211,26 @@ __global__ void k_finish_norm(const double* __restrict__ partial, int nblk, doub
     if (threadIdx.x == 0) scal[slot] = sqrt(s);
 }
 
+// After a Gram-Schmidt pass: scal[0] = ||w|| from the partial norms.  First pass
+// (second = 0): flags[1] = the second pass is needed (||w|| below 1/sqrt(2) of the
+// norm before, scal[5], or not a number).  Second pass: runs only when needed.
+__global__ void k_finish_pass(const double* __restrict__ partial, int nblk, double* __restrict__ scal,
+                              int* __restrict__ flags, int second) {
+    if (!gate_open(flags, second)) return;
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[b];
+    s = wave_sum<64>(s);
+    if (threadIdx.x == 0) {
+        const double nw = sqrt(s);
+        scal[0] = nw;
+        if (!second) flags[1] = !(nw >= kDgks * scal[5]);
+    }
+}
+
 // dst = src * (1 / scal[slot])
 __global__ void k_scale(const double2* __restrict__ src, double2* __restrict__ dst, int64_t N,
-                        const double* __restrict__ scal, int slot) {
+                        const double* __restrict__ scal, int slot, const int* __restrict__ flags = nullptr) {
+    if (!gate_open(flags, 0)) return;
     const double inv = 1.0 / scal[slot];
     for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
         dst[n] = make_double2(src[n].x * inv, src[n].y * inv);
@@ -183,17 +254,49 @@ __global__ void k_sum(const double2* __restrict__ a, const double2* __restrict__
         out[n] = make_double2(a[n].x + b[n].x, a[n].y + b[n].y);
 }
 
-// Givens update of Hessenberg column j (single thread; j < 128).
-// H is (m+1) x m column major; hcol holds h_0..h_j, scal[0] = ||w|| = h_{j+1}.
-// scal[1] = |g_{j+1}| (residual estimate, unnormalised).
-__global__ void k_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ hcol,
-                         double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
-                         double* __restrict__ scal) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+
+// One Arnoldi step's Givens update of Hessenberg column j and its stopping test, on the device:
+// the cycle stops on breakdown (||w|| = 0), when |g_{j+1}| / ||b|| (scal[2]) reaches
+// tol, or on a value that is not a number.  rec = {||w||, |g_{j+1}|, stop} for the
+// host; flags[2] counts the steps that took a second Gram-Schmidt pass.
+__global__ void k_givens_step(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ hcol,
+                              double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                              double* __restrict__ scal, int* __restrict__ flags, double tol, double* __restrict__ rec) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || flags[0] != 0) return;
     double2* col = H + (int64_t)j * ldh;
     for (int i = 0; i <= j; ++i) col[i] = hcol[i];
     col[j + 1] = make_double2(scal[0], 0.0);
-    scal[1] = givens_column(col, j, cs, sn, g);
+    const double est = givens_column(col, j, cs, sn, g);
+    scal[1] = est;
+    const double hn = scal[0];
+    const bool stop = hn == 0.0 || !(est / scal[2] > tol) || !isfinite(hn) || !isfinite(est);
+    flags[2] += flags[1];
+    flags[0] = stop ? 1 : 0;
+    rec[0] = hn;
+    rec[1] = est;
+    rec[2] = stop ? 1.0 : 0.0;
+}
+
+// A new cycle: g = (beta, 0, ..., 0) and the step flags cleared.
+__global__ void k_init_cycle(double2* __restrict__ g, int m, const double* __restrict__ scal, int slot,
+                             int* __restrict__ flags) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = make_double2(i == 0 ? scal[slot] : 0.0, 0.0);
+    if (threadIdx.x == 0) {
+        flags[0] = 0;
+        flags[1] = 0;
+    }
+}
+
+// h = h' + h after the second pass (when it ran)
+__global__ void k_add_dots(const double2* __restrict__ y, int nvec, double2* __restrict__ h,
+                           const int* __restrict__ flags) {
+    if (!gate_open(flags, 1)) return;
+    const int i = threadIdx.x;
+    if (i < nvec) h[i] = make_double2(y[i].x + h[i].x, y[i].y + h[i].y);
+}
+
+__global__ void k_zero_flags(int* __restrict__ flags) {
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0;
 }
 
 // y = R^-1 g on the leading k x k triangle (single thread)
@@ -203,10 +306,6 @@ __global__ void k_backsolve(const double2* __restrict__ H, int ldh, int k, const
     back_substitute(H, ldh, k, g, y);
 }
 
-// g = (beta, 0, ..., 0)
-__global__ void k_init_g(double2* __restrict__ g, int m, const double* __restrict__ scal, int slot) {
-    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = make_double2(i == 0 ? scal[slot] : 0.0, 0.0);
-}
 
 struct Work {
     double2 *V, *Zs, *xt, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
@@ -214,6 +313,8 @@ struct Work {
     double* mnorm;
     float2 *lo_in, *lo_out;
     double *cs, *scal, *npart;
+    int* flags;                    // per-solve step flags (see gate_open)
+    double* rec;                   // two step records {||w||, |g|, stop, -} read by the host
     double2* dpart;
     int64_t ldv;
 };
@@ -255,6 +356,8 @@ size_t work_layout(int64_t N, int m, Work* W, char* base, int precond = 0, int64
     w.g = (double2*)take(130 * 16);
     w.y = (double2*)take(128 * 16);
     w.scal = (double*)take(64 * 8);
+    w.flags = (int*)take(4 * 4);
+    w.rec = (double*)take(8 * 8);
     w.npart = (double*)take(kDotBlocks * 8);
     w.dpart = (double2*)take(size_t(kDotBlocks) * 128 * 16);
     if (W) *W = w;
@@ -300,12 +403,16 @@ struct Solver {
         return hipStreamSynchronize(s);
     }
 
-    // V^H w for vectors 0..nvec-1 into out (accumulate or overwrite)
-    void multidot(int nvec, const double2* w, double2* out, int accumulate) {
+    // V^H w for vectors 0..nvec-1 into out (accumulate or overwrite); with norm_slot >= 0
+    // also scal[norm_slot] = ||w||; gated by the step flags (second: the second pass)
+    void multidot(int nvec, const double2* w, double2* out, int accumulate, int norm_slot, int second) {
         dim3 grid(nblk, (nvec + kDotTile - 1) / kDotTile);
-        k_multidot<<<grid, 256, 0, s>>>(W.V, W.ldv, nvec, w, N, W.dpart);
-        k_reduce_partial<<<1, 128, 0, s>>>(W.dpart, nblk, nvec, out, accumulate);
+        double* np = norm_slot >= 0 ? W.npart : nullptr;
+        k_multidot<<<grid, 256, 0, s>>>(W.V, W.ldv, nvec, w, N, W.dpart, np, W.flags, second);
+        k_reduce_dots<<<nvec + (np ? 1 : 0), 256, 0, s>>>(W.dpart, nblk, nvec, out, accumulate, np, W.scal,
+                                                          norm_slot, W.flags, second);
     }
+    hipEvent_t ev[2] = {nullptr, nullptr};   // step records copied to host[16 + 4 (j & 1)]
 
     // Arnoldi's right preconditioner: 0 none, 1 block diagonal, 2 MLP.  With the
     // restart correction (precond 3) the cycles use the MLP's base map.
@@ -387,40 +494,49 @@ struct Solver {
             }
             // v_0 = r / beta
             k_scale<<<nblk, 256, 0, s>>>(W.r, W.V, N, W.scal, 3);
-            k_init_g<<<1, 256, 0, s>>>(W.g, m, W.scal, 3);
-            int jend = 0;
-            for (int j = 0; j < m; ++j) {
-                double2* vj = W.V + (int64_t)j * W.ldv;
-                const double2* zj = vj;
-                if (ipc) {
-                    double2* zz = W.Zs + (int64_t)j * W.ldv;
-                    if ((e = apply_precond(vj, zz)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-                    zj = zz;
+            k_init_cycle<<<1, 256, 0, s>>>(W.g, m, W.scal, 3, W.flags);
+            int jend = 0, pending = -1;
+            for (int j = 0; j <= m; ++j) {
+                const bool queue = j < m && *mv < max_mv;
+                if (queue) {
+                    double2* vj = W.V + (int64_t)j * W.ldv;
+                    const double2* zj = vj;
+                    if (ipc) {
+                        double2* zz = W.Zs + (int64_t)j * W.ldv;
+                        if ((e = apply_precond(vj, zz)) != hipSuccess)
+                            return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                        zj = zz;
+                    }
+                    if ((e = matvec(prec, zj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                    ++*mv;
+                    // classical Gram-Schmidt with ||w|| before it; repeated when the norm fell below
+                    // 1/sqrt(2) of that (the Daniel-Gragg-Kaufman-Stewart test), decided on the device
+                    multidot(j + 1, W.w, W.hcol, 0, 5, 0);                                 // h = V^H w, ||w||
+                    k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.hcol, -1.0, W.w, N, W.npart, W.flags, 0);
+                    k_finish_pass<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, W.flags, 0);    // ||w - V h||, test
+                    multidot(j + 1, W.w, W.y, 0, -1, 1);                                   // h' = V^H w
+                    k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.y, -1.0, W.w, N, W.npart, W.flags, 1);
+                    k_add_dots<<<1, 128, 0, s>>>(W.y, j + 1, W.hcol, W.flags);             // h += h'
+                    k_finish_pass<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, W.flags, 1);     // ||w||
+                    double* rec = W.rec + 4 * (j & 1);
+                    k_givens_step<<<1, 1, 0, s>>>(W.H, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal, W.flags, tol, rec);
+                    k_scale<<<nblk, 256, 0, s>>>(W.w, W.V + (int64_t)(j + 1) * W.ldv, N, W.scal, 0, W.flags);
+                    if ((e = hipMemcpyAsync(host + 16 + 4 * (j & 1), rec, 32, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                        (e = hipEventRecord(ev[j & 1], s)) != hipSuccess)
+                        return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
                 }
-                if ((e = matvec(prec, zj, W.w)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-                ++*mv;
-                ++*its;
-                // classical Gram-Schmidt, repeated when the norm fell below 1/sqrt(2) of ||w||
-                // (the Daniel-Gragg-Kaufman-Stewart test)
-                (void)norm_into(W.w, 5);                                                   // ||w|| before
-                multidot(j + 1, W.w, W.hcol, 0);                                           // h = V^H w
-                k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.hcol, -1.0, W.w, N, W.npart);
-                k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);                 // ||w - V h||
-                if ((e = fetch(6)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-                if (!(host[0] >= kDgks * host[5])) {
-                    multidot(j + 1, W.w, W.y, 0);                                          // h' = V^H w
-                    k_multiaxpy<<<nblk, 256, 0, s>>>(W.V, W.ldv, j + 1, W.y, -1.0, W.w, N, W.npart);
-                    k_reduce_partial<<<1, 128, 0, s>>>(W.y, 1, j + 1, W.hcol, 1);         // h += h'
-                    k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 0);             // ||w||
-                    ++reorth;
+                if (pending >= 0) {            // the previous step's record, read while this one runs
+                    if ((e = hipEventSynchronize(ev[pending & 1])) != hipSuccess)
+                        return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+                    const double* r = host + 16 + 4 * (pending & 1);
+                    if (!std::isfinite(r[0]) || !std::isfinite(r[1]))
+                        return handle_fail(H2_ERR_NUMERIC, "Arnoldi produced NaN or Inf");
+                    jend = pending + 1;
+                    ++*its;
+                    if (r[2] != 0.0) break;
                 }
-                k_givens<<<1, 1, 0, s>>>(W.H, m + 1, j, W.hcol, W.cs, W.sn, W.g, W.scal);
-                if ((e = fetch(2)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-                jend = j + 1;
-                const double hn = host[0], est = host[1] / bnorm;
-                if (!std::isfinite(hn) || !std::isfinite(est)) return handle_fail(H2_ERR_NUMERIC, "Arnoldi produced NaN or Inf");
-                if (hn == 0.0 || est <= tol || *mv >= max_mv) break;
-                k_scale<<<nblk, 256, 0, s>>>(W.w, W.V + (int64_t)(j + 1) * W.ldv, N, W.scal, 0);
+                if (!queue) break;
+                pending = j;
             }
             k_backsolve<<<1, 1, 0, s>>>(W.H, m + 1, jend, W.g, W.y);
             k_multiaxpy<<<nblk, 256, 0, s>>>(ipc ? W.Zs : W.V, W.ldv, jend, W.y, 1.0, x, N, nullptr);   // x += V y (Z y)
@@ -494,6 +610,14 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
     }
     if (hipHostMalloc((void**)&S.host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return handle_fail(H2_ERR_DEVICE, "pinned host allocation failed");
+    for (auto& ev : S.ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            for (auto& e2 : S.ev)
+                if (e2) (void)hipEventDestroy(e2);
+            (void)hipHostFree(S.host);
+            return handle_fail(H2_ERR_DEVICE, "event creation failed");
+        }
+    k_zero_flags<<<1, 64, 0, S.s>>>(S.W.flags);
     *rep = h2_gmres_report{};
     h2_status st;
     const double2* bb = (const double2*)b;
@@ -563,8 +687,15 @@ extern "C" h2_status h2_gmres_solve(h2_handle h, const void* b, void* x, const h
         rep->converged = (st == H2_OK);
     }
     rep->corrections = S.corrections;
+    {   // steps that took the second Gram-Schmidt pass, counted on the device
+        int fl[4] = {0, 0, 0, 0};
+        if (hipMemcpyAsync(fl, S.W.flags, sizeof(fl), hipMemcpyDeviceToHost, S.s) == hipSuccess &&
+            hipStreamSynchronize(S.s) == hipSuccess)
+            S.reorth = fl[2];
+    }
     rep->reorth = S.reorth;
     if (hipStreamSynchronize(S.s) != hipSuccess && st >= 0) st = handle_fail(H2_ERR_DEVICE, "solve synchronisation failed");
+    for (auto& ev : S.ev) (void)hipEventDestroy(ev);
     (void)hipHostFree(S.host);
     return st;
 }

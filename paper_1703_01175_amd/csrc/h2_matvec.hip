@@ -252,6 +252,223 @@ __global__ __launch_bounds__(256) void k_coupling(const int* __restrict__ row_cl
         coupling_rows<TB, TV, 64>(kt, ncols, S, src, Xh, Yh, co, red);
 }
 
+// ---------------------------------------------------------------- symmetric couplings
+// Row slot t streams only the blocks it owns (one of each unordered admissible pair
+// {t, s}; S_st = S_ts^T) and applies each twice: Y_t += S_ts X_s, and the column
+// sums S_ts^T X_t (3 complex per owned column) go to `part` for cluster s, which
+// adds them in k_coupling_recv.  Lanes: RL row lanes per column (RL = 4, 8, 16 for
+// k_t <= 16, 32, 64), 64 / RL columns per wave step; lane (cg, rl) holds rows
+// rl + RL q (q < 4) of its column, so each column's transposed sum is a butterfly
+// over RL neighbouring lanes, and the lane's X_t rows stay in registers.
+
+// DPP move of a double / float within 16-lane rows
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL, typename TV> __device__ __forceinline__ TV dpp_add(TV v) {
+    TV r;
+    r.x = v.x + dpp_mov<CTRL>(v.x);
+    r.y = v.y + dpp_mov<CTRL>(v.y);
+    return r;
+}
+constexpr int kDppXor1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppRor4 = 0x124;
+constexpr int kDppRor8 = 0x128;
+
+// Lane exchange across 16-lane rows (ds_bpermute on 32-bit halves).
+__device__ __forceinline__ double shfl_xor_r(double v, int m) {
+    const int lane = threadIdx.x & 63;
+    const int src = ((lane ^ m) & 63) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float shfl_xor_r(float v, int m) {
+    const int lane = threadIdx.x & 63;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, __float_as_int(v)));
+}
+
+// Sum over the RL neighbouring lanes of a column (butterfly; every lane gets the sum).
+template <int RL, typename TV> __device__ __forceinline__ TV col_sum(TV v) {
+    v = dpp_add<kDppXor1>(v);
+    v = dpp_add<kDppXor2>(v);
+    if constexpr (RL >= 8) v = dpp_add<kDppHalfMirror>(v);
+    if constexpr (RL >= 16) v = dpp_add<kDppMirror>(v);
+    return v;
+}
+
+template <int C, typename TV> __device__ __forceinline__ TV quad_bcast(TV v) {
+    constexpr int ctrl = C | (C << 2) | (C << 4) | (C << 6);     // quad_perm [C, C, C, C]
+    TV r;
+    r.x = dpp_mov<ctrl>(v.x);
+    r.y = dpp_mov<ctrl>(v.y);
+    return r;
+}
+
+// An integer zero the compiler cannot see through: LDS reads indexed with it stay in
+// the loop instead of being hoisted into registers (which would cost occupancy).
+__device__ __forceinline__ int opaque_zero() {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
+// Owned columns [0, nown) of the row come first in its storage: column j's rows are
+// at S + j k_t, its coefficient row of X at src[j] (read one step ahead).
+template <typename TB, typename TV, int RL>
+__device__ __forceinline__ void coupling_sym_row(int kt, int nown, const TB* __restrict__ S,
+                                                 const int* __restrict__ src, const TV* __restrict__ Xh,
+                                                 TV* __restrict__ yt, const TV* __restrict__ xt_src,
+                                                 TV* __restrict__ part, TV (*red)[3]) {
+    constexpr int CG = 64 / RL;          // columns per wave step
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int rl = lane % RL;
+    const int cg = lane / RL;
+    // X_t rows (zero beyond k_t) staged in the first 64 rows of red
+    for (int e = threadIdx.x; e < 64 * kNcomp; e += 256)
+        red[e / kNcomp][e % kNcomp] = e < kt * kNcomp ? xt_src[e] : czero<TV>();
+    __syncthreads();
+    TV acc[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[q][c] = czero<TV>();
+    int jn = w * CG + cg;
+    int sn = jn < nown ? src[jn] : 0;
+    for (int j0 = w * CG; j0 < nown; j0 += 4 * CG) {
+        const int j = j0 + cg;
+        const bool live = j < nown;
+        const int sj = sn;
+        jn = j + 4 * CG;
+        sn = jn < nown ? src[jn] : 0;
+        const TB* col = S + (int64_t)(live ? j : 0) * kt;
+        TB sv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = rl + RL * q;
+            if (live && r < kt) sv[q] = ldnt(col + r);
+            else { sv[q].x = 0; sv[q].y = 0; }
+        }
+        TV xs[3];
+        if constexpr (RL == 4) {         // lane rl < 3 fetches component rl; the quad shares it
+            const TV xl = (live && rl < 3) ? Xh[(int64_t)sj * kNcomp + rl] : czero<TV>();
+            xs[0] = quad_bcast<0>(xl);
+            xs[1] = quad_bcast<1>(xl);
+            xs[2] = quad_bcast<2>(xl);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xs[c] = live ? Xh[(int64_t)sj * kNcomp + c] : czero<TV>();
+        }
+        const int z = opaque_zero();
+        TV p0 = czero<TV>(), p1 = czero<TV>(), p2 = czero<TV>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) cfma(acc[q][c], sv[q], xs[c]);
+            const TV* xr = red[rl + RL * q + z];
+            cfma(p0, sv[q], xr[0]);
+            cfma(p1, sv[q], xr[1]);
+            cfma(p2, sv[q], xr[2]);
+        }
+        p0 = col_sum<RL>(p0);
+        p1 = col_sum<RL>(p1);
+        p2 = col_sum<RL>(p2);
+        // lane rl = c stores component c of the column's partial (selects, no indexing)
+        TV o = p2;
+        o.x = rl == 1 ? p1.x : o.x;
+        o.y = rl == 1 ? p1.y : o.y;
+        o.x = rl == 0 ? p0.x : o.x;
+        o.y = rl == 0 ? p0.y : o.y;
+        if (live && rl < 3) part[(int64_t)j * kNcomp + rl] = o;
+    }
+    // Y_t rows: sum over the column groups of each 16-lane row, the 4 rows of the wave
+    // and the 4 waves
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            TV v = acc[q][c];
+            if constexpr (RL == 4) { v = dpp_add<kDppRor4>(v); v = dpp_add<kDppRor8>(v); }
+            if constexpr (RL == 8) v = dpp_add<kDppRor8>(v);
+            v.x += shfl_xor_r(v.x, 16);
+            v.y += shfl_xor_r(v.y, 16);
+            v.x += shfl_xor_r(v.x, 32);
+            v.y += shfl_xor_r(v.y, 32);
+            acc[q][c] = v;
+        }
+    __syncthreads();                     // every wave is done with the X_t rows in red
+    if (lane < RL)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = rl + RL * q;
+            if (r < kt)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red[w * 64 + r][c] = acc[q][c];
+        }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kt * kNcomp; e += 256) {
+        const int r = e / kNcomp, c = e % kNcomp;
+        TV v = cadd(cadd(red[r][c], red[64 + r][c]), cadd(red[128 + r][c], red[192 + r][c]));
+        yt[e] = v;
+    }
+}
+
+template <typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_coupling_sym(const int* __restrict__ row_cl, const int64_t* __restrict__ row_off,
+                                                      const int* __restrict__ row_colptr, const int* __restrict__ colsrc,
+                                                      const int* __restrict__ row_nown, const int* __restrict__ row_pbase,
+                                                      const int* __restrict__ cl_rank, const int* __restrict__ cl_coef,
+                                                      const TB* __restrict__ coupling, const TV* __restrict__ Xh,
+                                                      TV* __restrict__ Yh, TV* __restrict__ part) {
+    __shared__ TV red[256][3];
+    const int slot = blockIdx.x;
+    const int t = row_cl[slot];
+    const int kt = cl_rank[t];
+    const int nown = row_nown[slot];
+    const TB* S = coupling + row_off[slot];
+    const int co = cl_coef[t];
+    const int* src = colsrc + row_colptr[slot];
+    TV* pt = part + (int64_t)row_pbase[slot] * kNcomp;
+    const TV* xt = Xh + (int64_t)co * kNcomp;
+    TV* yt = Yh + (int64_t)co * kNcomp;
+    if (kt <= 16)
+        coupling_sym_row<TB, TV, 4>(kt, nown, S, src, Xh, yt, xt, pt, red);
+    else if (kt <= 32)
+        coupling_sym_row<TB, TV, 8>(kt, nown, S, src, Xh, yt, xt, pt, red);
+    else
+        coupling_sym_row<TB, TV, 16>(kt, nown, S, src, Xh, yt, xt, pt, red);
+}
+
+// Y_s += the partials S_ts^T X_t of the blocks that land in row slot s (fixed order).
+template <typename TV>
+__global__ __launch_bounds__(64) void k_coupling_recv(const int* __restrict__ row_cl, const int* __restrict__ rptr,
+                                                      const int* __restrict__ rp, const int* __restrict__ cl_rank,
+                                                      const int* __restrict__ cl_coef, const TV* __restrict__ part,
+                                                      TV* __restrict__ Yh) {
+    const int slot = blockIdx.x;
+    const int a = rptr[slot], b = rptr[slot + 1];
+    if (a == b) return;
+    const int t = row_cl[slot];
+    const int n3 = cl_rank[t] * kNcomp;
+    TV* y = Yh + (int64_t)cl_coef[t] * kNcomp;
+    for (int e = threadIdx.x; e < n3; e += 64) {
+        TV acc = czero<TV>();
+#pragma unroll 8
+        for (int q = a; q < b; ++q) acc = cadd(acc, part[(int64_t)rp[q] * kNcomp + e]);
+        y[e] = cadd(y[e], acc);
+    }
+}
+
 // ---------------------------------------------------------------- downward pass
 // Y_c[b][c] += sum_a T_c[b, a] Y_p[a][c]
 template <typename TB, typename TV>
@@ -274,6 +491,55 @@ __global__ __launch_bounds__(64) void k_transfer_down(const int* __restrict__ li
         }
         TV* o = Yh + (int64_t)(cl_coef[ch] + b) * kNcomp;
         o[0] = cadd(o[0], acc0); o[1] = cadd(o[1], acc1); o[2] = cadd(o[2], acc2);
+    }
+}
+
+// Row `lane` of leaf t after a near pass (s0..s2: this pass's sums): with several
+// passes, the earlier ones leave their sums in ypart and stop; the last adds them,
+// the backward transformation V_t Y_t and the epilogue z = x + alpha y (op Z).
+template <typename TB, typename TV>
+__device__ __forceinline__ void near_finish_row(int t, int n, int lane, TV s0, TV s1, TV s2, int pass, int npass,
+                                                TV* __restrict__ ypart, const int* __restrict__ cl_rank,
+                                                const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
+                                                const int64_t* __restrict__ cl_basis_off, const TB* __restrict__ basis,
+                                                const TV* __restrict__ Yh, const int* __restrict__ perm,
+                                                const TV* __restrict__ x, TV* __restrict__ y, int op,
+                                                typename Real<TV>::T alpha) {
+    if (npass > 1) {   // rows of the earlier passes; all but the last pass stop here
+        TV* yp = ypart + (int64_t)(cl_begin[t] + lane) * kNcomp;
+        if (pass > 0) {
+            s0 = cadd(yp[0], s0);
+            s1 = cadd(yp[1], s1);
+            s2 = cadd(yp[2], s2);
+        }
+        if (pass < npass - 1) {
+            yp[0] = s0;
+            yp[1] = s1;
+            yp[2] = s2;
+            return;
+        }
+    }
+    const int k = cl_rank[t];
+    if (k > 0) {   // backward transformation at the leaf: y_t += V_t Y_t
+        const TB* V = basis + cl_basis_off[t];
+        const TV* yt = Yh + (int64_t)cl_coef[t] * kNcomp;
+        for (int a = 0; a < k; ++a) {
+            TB v = V[(int64_t)a * n + lane];
+            cfma(s0, v, yt[a * 3 + 0]);
+            cfma(s1, v, yt[a * 3 + 1]);
+            cfma(s2, v, yt[a * 3 + 2]);
+        }
+    }
+    const int vox = perm[cl_begin[t] + lane];
+    TV* yo = y + (int64_t)vox * kNcomp;
+    if (op == 1) {
+        const TV* xi = x + (int64_t)vox * kNcomp;
+        TV r;
+        r.x = xi[0].x + alpha * s0.x; r.y = xi[0].y + alpha * s0.y; yo[0] = r;
+        r.x = xi[1].x + alpha * s1.x; r.y = xi[1].y + alpha * s1.y; yo[1] = r;
+        r.x = xi[2].x + alpha * s2.x; r.y = xi[2].y + alpha * s2.y; yo[2] = r;
+    } else {
+        yo[0] = s0; yo[1] = s1; yo[2] = s2;
     }
 }
 
@@ -324,42 +590,8 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
         TV s0 = cadd(cadd(red[0][lane][0], red[1][lane][0]), cadd(red[2][lane][0], red[3][lane][0]));
         TV s1 = cadd(cadd(red[0][lane][1], red[1][lane][1]), cadd(red[2][lane][1], red[3][lane][1]));
         TV s2 = cadd(cadd(red[0][lane][2], red[1][lane][2]), cadd(red[2][lane][2], red[3][lane][2]));
-        if (npass > 1) {   // rows of the earlier passes; all but the last pass stop here
-            TV* yp = ypart + (int64_t)(cl_begin[t] + lane) * kNcomp;
-            if (pass > 0) {
-                s0 = cadd(yp[0], s0);
-                s1 = cadd(yp[1], s1);
-                s2 = cadd(yp[2], s2);
-            }
-            if (pass < npass - 1) {
-                yp[0] = s0;
-                yp[1] = s1;
-                yp[2] = s2;
-                return;
-            }
-        }
-        const int k = cl_rank[t];
-        if (k > 0) {   // backward transformation at the leaf: y_t += V_t Y_t
-            const TB* V = basis + cl_basis_off[t];
-            const TV* yt = Yh + (int64_t)cl_coef[t] * kNcomp;
-            for (int a = 0; a < k; ++a) {
-                TB v = V[(int64_t)a * n + lane];
-                cfma(s0, v, yt[a * 3 + 0]);
-                cfma(s1, v, yt[a * 3 + 1]);
-                cfma(s2, v, yt[a * 3 + 2]);
-            }
-        }
-        const int vox = perm[cl_begin[t] + lane];
-        TV* yo = y + (int64_t)vox * kNcomp;
-        if (op == 1) {
-            const TV* xi = x + (int64_t)vox * kNcomp;
-            TV r;
-            r.x = xi[0].x + alpha * s0.x; r.y = xi[0].y + alpha * s0.y; yo[0] = r;
-            r.x = xi[1].x + alpha * s1.x; r.y = xi[1].y + alpha * s1.y; yo[1] = r;
-            r.x = xi[2].x + alpha * s2.x; r.y = xi[2].y + alpha * s2.y; yo[2] = r;
-        } else {
-            yo[0] = s0; yo[1] = s1; yo[2] = s2;
-        }
+        near_finish_row<TB, TV>(t, n, lane, s0, s1, s2, pass, npass, ypart, cl_rank, cl_coef, cl_begin,
+                                cl_basis_off, basis, Yh, perm, x, y, op, alpha);
     }
 }
 
@@ -575,9 +807,9 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     auto begin = [&](int f) { if (prof) prof->begin(f, s); };
     auto end = [&](int f) { if (prof) prof->end(f, s); };
     // full mode over stored-once blocks: all passes but the last read only U, so they
-    // run on the side stream beside the upward pass, couplings and downward pass
-    // (kept in order when the kernel families are being timed)
-    const bool overlap = !prof && !d.near_sym && d.near_passes > 1 && d.near_side;
+    // run on the side stream beside the upward pass, couplings and downward pass (when
+    // the kernel families are timed, those passes are timed on the side stream)
+    const bool overlap = !d.near_sym && d.near_passes > 1 && d.near_side;
     auto near_kernel = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
     auto near_pass = [&](int pass, const TV* xr, TV* yr, hipStream_t st) {
         const int np = d.near_passes;
@@ -596,7 +828,9 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             hipError_t e = hipEventRecord(d.near_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(d.near_side, d.near_fork, 0);
             if (e != hipSuccess) return e;
+            if (prof) prof->begin(5, d.near_side);
             for (int pass = 0; pass + 1 < d.near_passes; ++pass) near_pass(pass, xr, yr, d.near_side);
+            if (prof) prof->end(5, d.near_side);
             if ((e = hipEventRecord(d.near_join, d.near_side)) != hipSuccess) return e;
         }
         if (d.coef_rows > 0) {
@@ -612,9 +846,20 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                         transfer, Xh);
             end(2);
             begin(3);
-            k_coupling<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr, d.colsrc,
-                                                         d.cl_rank, d.cl_coef, coupling, Xh, Yh);
-            end(3);
+            if (d.coup_sym) {
+                k_coupling_sym<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_off, d.row_colptr, d.colsrc,
+                                                                 d.row_nown, d.row_pbase, d.cl_rank, d.cl_coef,
+                                                                 coupling, Xh, Yh, (TV*)d.cpart);
+                end(3);
+                begin(7);
+                k_coupling_recv<TV><<<d.n_rowcl, 64, 0, s>>>(d.row_cl, d.crecv_ptr, d.crecv_p, d.cl_rank, d.cl_coef,
+                                                             (const TV*)d.cpart, Yh);
+                end(7);
+            } else {
+                k_coupling<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr,
+                                                             d.colsrc, d.cl_rank, d.cl_coef, coupling, Xh, Yh);
+                end(3);
+            }
             begin(4);
             for (int l = 0; l < lv.n_down; ++l)
                 if (lv.down_count[l] > 0)
@@ -622,6 +867,10 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                             d.cl_coef, d.cl_parent, d.cl_transfer_off,
                                                                             transfer, Yh);
             end(4);
+        }
+        if (overlap) {                   // the last pass waits for the side stream's passes
+            hipError_t e = hipStreamWaitEvent(s, d.near_join, 0);
+            if (e != hipSuccess) return e;
         }
         begin(5);
         if (d.near_sym) {
@@ -636,8 +885,6 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                 Yh, d.perm, xr, yr, op, alpha);
             end(6);
         } else if (overlap) {
-            hipError_t e = hipStreamWaitEvent(s, d.near_join, 0);
-            if (e != hipSuccess) return e;
             near_pass(d.near_passes - 1, xr, yr, s);
             end(5);
         } else {

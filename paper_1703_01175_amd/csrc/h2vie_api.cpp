@@ -75,6 +75,15 @@ struct Plan {
     size_t o_sym[7] = {0, 0, 0, 0, 0, 0, 0}, o_symoff = 0, o_sympart = 0, o_symrows = 0;
     std::vector<int> row_cl, row_ncols, row_colptr, colsrc;
     std::vector<int64_t> row_off;
+    // symmetric couplings (empty when S_st != S_ts^T somewhere): each unordered admissible
+    // pair streamed once by its owner; per row slot the owned columns (their storage
+    // column in the grouped row and coefficient row), their first partial column, and the
+    // partial columns (first column of each block) that land in the slot's cluster
+    bool csym = false;
+    std::vector<int> row_nown, row_pbase, crecv_ptr, crecv_p;
+    std::vector<int64_t> coup_dev_off;      // per far pair: element offset of its block on the device
+    int64_t csym_elems = 0, csym_cols = 0;
+    size_t o_csym[4] = {0, 0, 0, 0}, o_cpart = 0;
     std::vector<int> up_list, down_list;
     std::vector<int> lc_beg, lc_size;           // leaves in cluster order
     std::vector<int64_t> lc_diag, lc_inv;
@@ -374,6 +383,100 @@ static void plan_symmetric_near(const h2_host_desc* d, const std::vector<int64_t
     P.sym = true;
 }
 
+// Symmetric couplings: when every admissible pair (t, s) has its mirror (s, t) with
+// S_st = S_ts^T bit for bit (checked here on host threads), the product can stream
+// each unordered pair once.  The pair goes to t when (t < s) equals (t + s even),
+// else to s: every cluster owns about half of its pairs wherever it sits in the
+// numbering.  Each grouped block row is stored with its owned blocks first (the
+// symmetric kernel streams that leading part; the full kernel the whole row, its
+// gather index reordered alike).  Ranks above 4 * 16 rows per lane group are not
+// handled (the mode is then not offered).  Needs P.row_cl / row_colptr / colsrc.
+void plan_symmetric_couplings(const h2_host_desc* d, const std::vector<int64_t>& ffirst,
+                              const std::vector<int64_t>& fcount, Plan& P) {
+    const int nc = d->n_clusters;
+    if (d->n_far == 0 || P.max_rank > 64) return;
+    // each row's partners sorted, to find the mirror of a pair
+    std::vector<std::pair<int, int64_t>> sorted(size_t(d->n_far));
+    for (int t = 0; t < nc; ++t) {
+        if (ffirst[t] < 0) continue;
+        for (int64_t i = ffirst[t]; i < ffirst[t] + fcount[t]; ++i) sorted[size_t(i)] = {d->far_s[i], i};
+        std::sort(sorted.begin() + ffirst[t], sorted.begin() + ffirst[t] + fcount[t]);
+    }
+    std::vector<int64_t> mirror(size_t(d->n_far), -1);
+    for (int64_t i = 0; i < d->n_far; ++i) {
+        const int t = d->far_t[i], s = d->far_s[i];
+        if (ffirst[s] < 0) return;
+        auto b = sorted.begin() + ffirst[s], e = b + fcount[s];
+        auto it = std::lower_bound(b, e, std::pair<int, int64_t>(t, -1));
+        if (it == e || it->first != t) return;
+        mirror[size_t(i)] = it->second;
+    }
+    std::atomic<bool> same(true);
+    auto check = [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b && same.load(std::memory_order_relaxed); ++i) {
+            const int t = d->far_t[i], s = d->far_s[i];
+            if (t >= s) continue;
+            const int kt = d->rank[t], ks = d->rank[s];
+            const double* sts = d->coupling + 2 * d->far_off[i];                 // kt x ks, column major
+            const double* sst = d->coupling + 2 * d->far_off[mirror[size_t(i)]];  // ks x kt, column major
+            for (int c = 0; c < ks; ++c)
+                for (int r = 0; r < kt; ++r)
+                    if (std::memcmp(sts + 2 * (int64_t(c) * kt + r), sst + 2 * (int64_t(r) * ks + c), 16) != 0) {
+                        same.store(false);
+                        return;
+                    }
+        }
+    };
+    const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(8, d->n_far / 65536 + 1));
+    std::vector<std::thread> th;
+    for (int64_t k = 0; k < nth; ++k) th.emplace_back(check, d->n_far * k / nth, d->n_far * (k + 1) / nth);
+    for (auto& x : th) x.join();
+    if (!same.load()) return;
+    auto owner = [](int t, int s) { return ((t < s) == (((t + s) & 1) == 0)) ? t : s; };
+    const size_t nrow = P.row_cl.size();
+    std::vector<int> slot_of(nc, -1);
+    for (size_t q = 0; q < nrow; ++q) slot_of[P.row_cl[q]] = int(q);
+    std::vector<std::vector<int>> recv(nrow);
+    std::vector<int> row_nown(nrow, 0), row_pbase(nrow, 0), colsrc(P.colsrc);
+    std::vector<int64_t> dev_off(size_t(d->n_far), 0);
+    int64_t pcols = 0, elems = 0;
+    for (size_t q = 0; q < nrow; ++q) {
+        const int t = P.row_cl[q], kt = d->rank[t];
+        row_pbase[q] = int(pcols);
+        if (ffirst[t] < 0) continue;
+        int col = 0;
+        int64_t pos = P.row_colptr[q];
+        for (int pass = 0; pass < 2; ++pass)            // owned blocks first, then the others
+            for (int64_t i = ffirst[t]; i < ffirst[t] + fcount[t]; ++i) {
+                const int s = d->far_s[i], ks = d->rank[s];
+                const bool own = owner(t, s) == t;
+                if (own != (pass == 0)) continue;
+                dev_off[size_t(i)] = P.row_off[q] + int64_t(col) * kt;
+                for (int b = 0; b < ks; ++b) colsrc[size_t(pos++)] = P.cl_coef[s] + b;
+                if (own) {
+                    recv[size_t(slot_of[s])].push_back(int(pcols + col));
+                    elems += int64_t(kt) * ks;
+                    row_nown[q] += ks;
+                }
+                col += ks;
+            }
+        pcols += row_nown[q];
+        if (pcols >= (int64_t(1) << 31) / kNcomp) return;
+    }
+    P.row_nown = std::move(row_nown);
+    P.row_pbase = std::move(row_pbase);
+    P.colsrc = std::move(colsrc);
+    P.coup_dev_off = std::move(dev_off);
+    P.csym_elems = elems;
+    P.csym_cols = pcols;
+    P.crecv_ptr.assign(1, 0);
+    for (size_t q = 0; q < nrow; ++q) {
+        for (int p : recv[q]) P.crecv_p.push_back(p);
+        P.crecv_ptr.push_back(int(P.crecv_p.size()));
+    }
+    P.csym = true;
+}
+
 h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     h2_status st = validate(d);
     if (st != H2_OK) return st;
@@ -498,6 +601,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         }
         if (P.colsrc.size() >= (size_t(1) << 31)) return fail(H2_ERR_BAD_DESC, "too many coupling columns");
     }
+    plan_symmetric_couplings(d, ffirst, fcount, P);
 
     // level lists: upward (deepest parents first), downward (top children first)
     for (int l = P.depth - 1; l >= 0; --l) {
@@ -532,12 +636,18 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     P.o_nss = L.add(ints(P.near_ssize.size()));
     P.o_noff = L.add(i64s(P.near_off.size()));
     P.o_npass = L.add(ints(P.near_pass_ptr.size()));
+
     if (P.near_passes > 1) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
     P.o_rowcl = L.add(ints(P.row_cl.size()));
     P.o_rownc = L.add(ints(P.row_ncols.size()));
     P.o_rowcp = L.add(ints(P.row_colptr.size()));
     P.o_colsrc = L.add(ints(P.colsrc.size()));
     P.o_rowoff = L.add(i64s(P.row_off.size()));
+    if (P.csym) {
+        const std::vector<int>* cv[4] = {&P.row_nown, &P.row_pbase, &P.crecv_ptr, &P.crecv_p};
+        for (int q = 0; q < 4; ++q) P.o_csym[q] = L.add(ints(cv[q]->size()));
+        P.o_cpart = L.add(size_t(std::max<int64_t>(P.csym_cols, 1)) * kNcomp * 16);
+    }
     P.o_up = L.add(ints(P.up_list.size()));
     P.o_lbeg = L.add(ints(P.lc_beg.size()));
     P.o_lsize = L.add(ints(P.lc_size.size()));
@@ -562,7 +672,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     if (P.tiers & 4) {
         P.batch = new BatchHost();
         BatchHost& B = *P.batch;
-        h2_status bs = plan_batch(d, o->max_rhs, P.near_uoff.data(), B);
+        h2_status bs = plan_batch(d, o->max_rhs, P.near_uoff.data(), P.csym ? P.coup_dev_off.data() : nullptr, B);
         if (bs != H2_OK) return fail(bs, "batched tier needs ranks <= 64 and fewer than 2^31 padded rows");
         const size_t cols = size_t(B.max_cols);
         P.o_arena = L.add(size_t(std::max<int64_t>(B.arena_elems, 1)) * 2);
@@ -643,11 +753,16 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     errs.push_back(put(P.o_nss, P.near_ssize.data(), P.near_ssize.size() * 4));
     errs.push_back(put(P.o_noff, P.near_off.data(), P.near_off.size() * 8));
     errs.push_back(put(P.o_npass, P.near_pass_ptr.data(), P.near_pass_ptr.size() * 4));
+
     errs.push_back(put(P.o_rowcl, P.row_cl.data(), P.row_cl.size() * 4));
     errs.push_back(put(P.o_rownc, P.row_ncols.data(), P.row_ncols.size() * 4));
     errs.push_back(put(P.o_rowcp, P.row_colptr.data(), P.row_colptr.size() * 4));
     errs.push_back(put(P.o_colsrc, P.colsrc.data(), P.colsrc.size() * 4));
     errs.push_back(put(P.o_rowoff, P.row_off.data(), P.row_off.size() * 8));
+    if (P.csym) {
+        const std::vector<int>* cv[4] = {&P.row_nown, &P.row_pbase, &P.crecv_ptr, &P.crecv_p};
+        for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_csym[q], cv[q]->data(), cv[q]->size() * 4));
+    }
     errs.push_back(put(P.o_up, P.up_list.data(), P.up_list.size() * 4));
     errs.push_back(put(P.o_lbeg, P.lc_beg.data(), P.lc_beg.size() * 4));
     errs.push_back(put(P.o_lsize, P.lc_size.data(), P.lc_size.size() * 4));
@@ -670,6 +785,22 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
             std::memcpy(near_staged.data() + 2 * P.near_uoff[i], d->near_blocks + 2 * d->near_off[i], size_t(n) * 16);
         }
         src[0] = near_staged.data();
+    }
+    std::vector<double> coup_staged;        // grouped rows with their owned blocks first
+    if (P.csym) {
+        coup_staged.resize(size_t(2 * d->coupling_len));
+        auto fill = [&](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i) {
+                const int64_t n = int64_t(d->rank[d->far_t[i]]) * d->rank[d->far_s[i]];
+                std::memcpy(coup_staged.data() + 2 * P.coup_dev_off[size_t(i)], d->coupling + 2 * d->far_off[i],
+                            size_t(n) * 16);
+            }
+        };
+        const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(8, d->n_far / 65536 + 1));
+        std::vector<std::thread> th;
+        for (int64_t k = 0; k < nth; ++k) th.emplace_back(fill, d->n_far * k / nth, d->n_far * (k + 1) / nth);
+        for (auto& x : th) x.join();
+        src[1] = coup_staged.data();
     }
     for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_data[0][q], src[q], size_t(lens[q]) * 16));
     for (hipError_t e : errs)
@@ -724,6 +855,15 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.row_colptr = (const int*)(base + P.o_rowcp);
     D.colsrc = (const int*)(base + P.o_colsrc);
     D.row_off = (const int64_t*)(base + P.o_rowoff);
+    if (P.csym) {
+        D.coup_sym_ok = true;
+        D.coup_sym = true;
+        D.row_nown = (const int*)(base + P.o_csym[0]);
+        D.row_pbase = (const int*)(base + P.o_csym[1]);
+        D.crecv_ptr = (const int*)(base + P.o_csym[2]);
+        D.crecv_p = (const int*)(base + P.o_csym[3]);
+        D.cpart = base + P.o_cpart;
+    }
     D.up_list = (const int*)(base + P.o_up);
     D.leaves.n = int(P.lc_beg.size());
     D.leaves.beg = (const int*)(base + P.o_lbeg);
@@ -736,6 +876,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.near_cached = P.near_dedup;
     D.near_passes = P.near_passes;
     D.near_pass_ptr = (const int*)(base + P.o_npass);
+
     D.near_ypart = P.near_passes > 1 ? base + P.o_ypart : nullptr;
     if (P.near_passes > 1) {   // side stream (default priority) for the passes that need only U
         hipStream_t side = nullptr;
@@ -829,6 +970,9 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     S.near_elems = d->near_len;
     S.near_stored_elems = P.near_stored_len;
     S.near_unique = P.near_dedup ? int64_t(P.near_src.size()) : d->n_near;
+    S.near_passes = D.near_passes;
+    S.coupling_owned_elems = P.csym ? P.csym_elems : 0;
+    S.coupling_owned_cols = P.csym ? P.csym_cols : 0;
     S.coupling_elems = d->coupling_len;
     S.basis_elems = d->basis_len;
     S.transfer_elems = d->transfer_len;
@@ -884,6 +1028,17 @@ h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* 
                        : launch_matvec(h->dev, h->lv, int(op), int(p), x, y, n_rhs, ld,
                                        reinterpret_cast<hipStream_t>(stream), h->prof);
     if (e != hipSuccess) return fail(H2_ERR_DEVICE, "matvec launch failed: %s", hipGetErrorString(e));
+    return H2_OK;
+}
+
+h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (set < -1 || set > 1) return fail(H2_ERR_INVALID_ARG, "coupling mode must be -1, 0 or 1");
+    if (set == 1 && !h->dev.coup_sym_ok)
+        return fail(H2_ERR_INVALID_ARG, "the couplings are not symmetric: no symmetric coupling mode");
+    if (set >= 0) h->dev.coup_sym = set == 1;
+    if (mode) *mode = h->dev.coup_sym ? 1 : 0;
+    if (available) *available = h->dev.coup_sym_ok ? 1 : 0;
     return H2_OK;
 }
 

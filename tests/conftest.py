@@ -20,6 +20,11 @@ def built(name):
     """Session cache of small seeded H^2 representations used by several tests."""
     if name in _CACHE:
         return _CACHE[name]
+    if name.endswith("_sym"):                 # couplings symmetrised (S_st = S_ts^T bit for bit)
+        from h2gen.construct import symmetrize_couplings
+        g, d = built(name[:-4])
+        _CACHE[name] = (g, symmetrize_couplings(d))
+        return _CACHE[name]
     import h2gen
     from h2gen.construct import build_h2
     from h2gen.geometry import box

@@ -167,3 +167,26 @@ def test_bad_handles_without_gpu():
     lib.h2_destroy(None)
     lib.h2_destroy(fake)    # unknown pointers are ignored
     assert lib.h2_profile_enable(fake, 1) == -5
+
+
+def test_plan_reserves_coupling_partials_only_for_symmetric_couplings():
+    """A description with symmetrised couplings (S_st = S_ts^T bit for bit, checked
+    by the plan) gets the symmetric coupling mode's buffers: one 3-complex partial
+    per owned column (each unordered admissible pair owned by one of its clusters,
+    about half of every cluster's pairs) plus the receive lists.  The
+    generator's own couplings (eq. (18), not exact transposes) get none."""
+    from conftest import built
+    d0 = built("rod")[1]
+    d = built("rod_sym")[1]
+    st0, n0 = _plan(d0, flags=1)
+    st, n = _plan(d, flags=1)
+    assert st0 == 0 and st == 0
+    own = 0
+    for t, s in zip(d.far_t, d.far_s):
+        t, s = int(t), int(s)
+        owner = t if (t < s) == ((t + s) % 2 == 0) else s
+        if owner == t:
+            own += int(d.rank[s])
+    total_cols = int(d.rank[d.far_s].sum())
+    assert 0.4 * total_cols <= own <= 0.6 * total_cols
+    assert n - n0 >= own * 3 * 16

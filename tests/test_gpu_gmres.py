@@ -44,7 +44,7 @@ def test_gmres_fp64_converges(torch, name):
     assert _true_res(d, x, b) <= 1.0001e-6
 
 
-@pytest.mark.parametrize("name", ["rod", "cube12"])
+@pytest.mark.parametrize("name", ["rod", "cube12", "rod_sym"])
 def test_gmres_iterations_match_oracle(torch, name):
     # the oracle's Arnoldi takes the device's selective second pass (DGKS): the same
     # iteration count and the same number of second passes

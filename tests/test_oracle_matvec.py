@@ -61,6 +61,32 @@ def test_complex_symmetry(name):
     assert asym <= d.meta["eps"] * np.linalg.norm(x) * np.linalg.norm(Hy)
 
 
+@pytest.mark.parametrize("name", ["rod", "slab", "cube16", "box9"])
+def test_symmetrized_couplings(name):
+    """Couplings averaged with the transposes of their mirror blocks (S_st := S_ts^T):
+    every stored pair is an exact transpose, the represented G is then symmetric to
+    rounding (P8 with symmetric storage), and the representation keeps its accuracy
+    against the dense G."""
+    g, d0 = built(name)
+    _, d = built(name + "_sym")
+    assert d.meta.get("symmetric_couplings") and not d0.meta.get("symmetric_couplings")
+    rev = {(int(t), int(s)): i for i, (t, s) in enumerate(zip(d.far_t, d.far_s))}
+    for i, (t, s) in enumerate(zip(d.far_t, d.far_s)):
+        j = rev[(int(s), int(t))]
+        assert np.array_equal(om._coupling(d, i), om._coupling(d, j).T)
+        if t < s:
+            mean = 0.5 * (om._coupling(d0, i) + om._coupling(d0, j).T)
+            assert np.array_equal(om._coupling(d, i), mean)
+    x = h2gen.random_vector(3 * g.n_vox, 2)
+    y = h2gen.random_vector(3 * g.n_vox, 3)
+    Hx, Hy = om.h2_matvec(d, x, "G"), om.h2_matvec(d, y, "G")
+    assert abs(x @ Hy - y @ Hx) <= 1e-14 * np.linalg.norm(x) * np.linalg.norm(Hy)
+    H0x = om.h2_matvec(d0, x, "G")
+    eps = d.meta["eps"]
+    yd = dense_Z_matvec(g.shape, g.h, g.k, g.chi, g.sigma, x, "G")
+    assert _err(Hx, yd) < eps and _err(Hx, H0x) < eps
+
+
 def test_epsilon_tightens_error():
     g = h2gen.cube(12, 0.5, 4.0)
     from h2gen.construct import build_h2
