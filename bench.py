@@ -244,12 +244,17 @@ def main():
         Hs = H2Operator(d, tiers=("fp64",), device="cuda:0", keep_all_near=True)
         log(f"[bench] streamed-near upload {time.time() - t0:.1f}s")
         streamed = {}
-        for mode in ("symmetric", "full"):
-            Hs.near_mode(mode == "symmetric")
-            streamed[mode] = product_leg(Hs, d, x, y, args.steps, args.warmup, args.workload)
+        coup_ok = Hs.coupling_mode()[1]
+        for near_sym, coup_sym in ((True, True), (False, True), (True, False)):
+            if coup_sym and not coup_ok:
+                continue
+            Hs.near_mode(near_sym)
+            Hs.coupling_mode(coup_sym)
+            key = f"near_{'sym' if near_sym else 'full'}_coupling_{'sym' if coup_sym else 'full'}"
+            streamed[key] = product_leg(Hs, d, x, y, args.steps, args.warmup, args.workload)
             ys = y.cpu().numpy()
-            streamed[mode]["max_rel_diff_vs_headline"] = float(np.linalg.norm(ys - result_gpu) /
-                                                               np.linalg.norm(result_gpu))
+            streamed[key]["max_rel_diff_vs_headline"] = float(np.linalg.norm(ys - result_gpu) /
+                                                              np.linalg.norm(result_gpu))
         extra["streamed_near"] = streamed
         Hs.close()
         del Hs

@@ -156,11 +156,12 @@ h2_status h2_matvec(h2_handle h, h2_op op, h2_precision p, const void* x, void* 
                     int64_t ld, void* stream);
 
 /* NONE: plain GMRES.  BLOCKDIAG, MLP: flexible GMRES with z_j = P(v_j) on every
- * Arnoldi vector.  MLP_RESTART: at the start of every cycle, x + P(r) with the
- * attached MLP map replaces x when it lowers ||b - Z x|| (one extra product per
- * cycle); the cycles themselves run with the MLP's base map (none or block
- * diagonal) as right preconditioner.  The network sees true residuals only, the
- * inputs it was trained on. */
+ * Arnoldi vector.  MLP_RESTART: at the start of every cycle, c = P(r) with the
+ * attached MLP map and w = Z c (one extra product per cycle) give the step
+ * x += alpha c with alpha = w^H r / ||w||^2, the multiple of c that minimises
+ * ||b - Z x|| (no step when w = 0); the cycles themselves run with the MLP's base
+ * map (none or block diagonal) as right preconditioner.  The network sees true
+ * residuals only, the inputs it was trained on. */
 typedef enum {
     H2_PRECOND_NONE = 0,
     H2_PRECOND_BLOCKDIAG = 1,
@@ -186,7 +187,7 @@ typedef struct {
     int32_t restarts;       /* GMRES cycles */
     int32_t outer;          /* refinement steps (0 for FP64) */
     double rel_residual;    /* true ||b - Z x|| / ||b||, FP64 product */
-    int32_t corrections;    /* accepted learned restart corrections (PRECOND_MLP_RESTART) */
+    int32_t corrections;    /* learned restart corrections applied (PRECOND_MLP_RESTART, alpha != 0) */
     int32_t reorth;         /* Arnoldi steps that took a second Gram-Schmidt pass */
 } h2_gmres_report;
 

@@ -56,7 +56,8 @@ DGKS = 1.0 / np.sqrt(2.0)   # reorthogonalise when ||w|| drops below this fracti
 def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec: int = 10000,
           x0: np.ndarray | None = None, precond=None, correct=None, ortho: str = "dgks") -> tuple:
     """Solve A x = b.  apply(v) -> A v; precond(v) -> z (right preconditioner, may be nonlinear).
-    correct(r) -> c: at every cycle start x + c replaces x when it lowers ||b - A x|| (one product).
+    correct(r) -> c: at every cycle start, the step x += alpha c with alpha = (A c)^H r / ||A c||^2,
+    the multiple of c that minimises ||b - A (x + alpha c)|| (one product; no step when A c = 0).
     ortho: "dgks" (second Gram-Schmidt pass only when needed) or "cgs2" (always two)."""
     if ortho not in ("dgks", "cgs2"):
         raise ValueError(ortho)
@@ -84,11 +85,14 @@ def gmres(apply, b: np.ndarray, tol: float = 1e-6, restart: int = 50, max_matvec
         if rel <= tol or mv >= max_matvec:
             return x, SolveReport(rel <= tol, its, mv, restarts, rel, hist, corrections, reorth)
         if correct is not None:
-            xt = x + correct(r)
-            rt = b - apply(xt)
+            c = correct(r)
+            w = apply(c)
             mv += 1
-            if float(np.linalg.norm(rt)) < beta:
-                x, r = xt, rt
+            ww = float(np.vdot(w, w).real)
+            alpha = np.vdot(w, r) / ww if ww > 0.0 else 0.0
+            if alpha != 0.0 and np.isfinite(alpha):
+                x = x + alpha * c
+                r = r - alpha * w
                 corrections += 1
                 beta = float(np.linalg.norm(r))
                 rel = beta / bnorm

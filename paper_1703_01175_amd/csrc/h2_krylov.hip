@@ -248,11 +248,6 @@ __global__ void k_add(double2* __restrict__ x, const double2* __restrict__ d, in
     }
 }
 
-// out = a + b
-__global__ void k_sum(const double2* __restrict__ a, const double2* __restrict__ b, double2* __restrict__ out, int64_t N) {
-    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
-        out[n] = make_double2(a[n].x + b[n].x, a[n].y + b[n].y);
-}
 
 
 // One Arnoldi step's Givens update of Hessenberg column j and its stopping test, on the device:
@@ -275,6 +270,50 @@ __global__ void k_givens_step(double2* __restrict__ H, int ldh, int j, const dou
     rec[0] = hn;
     rec[1] = est;
     rec[2] = stop ? 1.0 : 0.0;
+}
+
+// Minimal-residual step of the restart correction: alpha = w^H r / ||w||^2 from the dot
+// (hc[0]) and the partial norms of w; scal[10..11] = alpha (0 when ||w|| = 0 or alpha is
+// not a number).
+__global__ void k_mr_alpha(const double* __restrict__ partial, int nblk, const double2* __restrict__ hc,
+                           double* __restrict__ scal) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[b];
+    s = wave_sum<64>(s);
+    if (threadIdx.x == 0) {
+        double ar = 0.0, ai = 0.0;
+        if (s > 0.0) {
+            ar = hc[0].x / s;
+            ai = hc[0].y / s;
+            if (!isfinite(ar) || !isfinite(ai)) ar = ai = 0.0;
+        }
+        scal[10] = ar;
+        scal[11] = ai;
+    }
+}
+
+// x += alpha c, r -= alpha w (alpha = scal[10..11]); partial squared norms of the new r
+__global__ __launch_bounds__(256) void k_mr_step(double2* __restrict__ x, const double2* __restrict__ c,
+                                                 double2* __restrict__ r, const double2* __restrict__ w, int64_t N,
+                                                 const double* __restrict__ scal, double* __restrict__ nrm_partial) {
+    __shared__ double red[4];
+    const double ar = scal[10], ai = scal[11];
+    double nn = 0;
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        const double2 cv = c[n], wv = w[n];
+        double2 xv = x[n], rv = r[n];
+        xv.x += ar * cv.x - ai * cv.y;
+        xv.y += ar * cv.y + ai * cv.x;
+        rv.x -= ar * wv.x - ai * wv.y;
+        rv.y -= ar * wv.y + ai * wv.x;
+        x[n] = xv;
+        r[n] = rv;
+        nn += rv.x * rv.x + rv.y * rv.y;
+    }
+    nn = wave_sum<64>(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) nrm_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // A new cycle: g = (beta, 0, ..., 0) and the step flags cleared.
@@ -308,7 +347,7 @@ __global__ void k_backsolve(const double2* __restrict__ H, int ldh, int k, const
 
 
 struct Work {
-    double2 *V, *Zs, *xt, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
+    double2 *V, *Zs, *w, *r, *z, *d, *xs, *hcol, *H, *sn, *g, *y;
     float *mX, *mH1, *mH2, *mY;
     double* mnorm;
     float2 *lo_in, *lo_out;
@@ -334,7 +373,6 @@ size_t work_layout(int64_t N, int m, Work* W, char* base, int precond = 0, int64
     w.ldv = ldv;
     w.V = (double2*)take(size_t(ldv) * (m + 1) * 16);
     w.Zs = precond ? (double2*)take(size_t(ldv) * m * 16) : nullptr;
-    w.xt = precond == 3 ? (double2*)take(N * 16) : nullptr;
     if (precond >= 2) {
         w.mX = (float*)take(size_t(nleaf) * n_in * 4);
         w.mH1 = (float*)take(size_t(nleaf) * n_hidden * 4);
@@ -424,25 +462,26 @@ struct Solver {
         return mlp_apply_handle(h, v, z, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s);
     }
 
-    // Learned correction at a cycle start: x_try = x + P(r) with the attached MLP map;
-    // kept (x, r, beta and scal[3] replaced) only when ||rhs - Z x_try|| < beta.
-    h2_status restart_correction(int prec, const double2* rhs, double2* x, double* beta, int* mv) {
+    // Learned correction at a cycle start: c = P(r) with the attached MLP map, w = Z c,
+    // and the step x += alpha c, r -= alpha w with alpha = w^H r / ||w||^2 (the multiple
+    // of c that minimises the residual; none when w = 0).  beta and scal[3] follow r.
+    h2_status restart_correction(int prec, double2* x, double* beta, int* mv) {
         hipError_t e;
         if ((e = mlp_apply_handle(h, W.r, W.w, W.mX, W.mH1, W.mH2, W.mY, W.mnorm, s)) != hipSuccess)
             return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-        k_sum<<<nblk, 256, 0, s>>>(x, W.w, W.xt, N);
-        if ((e = matvec(prec, W.xt, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        if ((e = matvec(prec, W.w, W.z)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         ++*mv;
-        k_residual<<<nblk, 256, 0, s>>>(rhs, W.z, W.w, N, W.npart);
+        k_multidot<<<dim3(nblk, 1), 256, 0, s>>>(W.z, W.ldv, 1, W.r, N, W.dpart, nullptr, nullptr, 0);   // w^H r
+        k_reduce_dots<<<1, 256, 0, s>>>(W.dpart, nblk, 1, W.hcol, 0, nullptr, W.scal, 0, nullptr, 0);
+        k_norm2<<<nblk, 256, 0, s>>>(W.z, N, W.npart);                                             // ||w||^2
+        k_mr_alpha<<<1, 64, 0, s>>>(W.npart, nblk, W.hcol, W.scal);
+        k_mr_step<<<nblk, 256, 0, s>>>(x, W.w, W.r, W.z, N, W.scal, W.npart);
         k_finish_norm<<<1, 64, 0, s>>>(W.npart, nblk, W.scal, 4);
-        if ((e = fetch(5)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-        const double bt = host[4];
-        if (std::isfinite(bt) && bt < *beta) {
-            if ((e = hipMemcpyAsync(x, W.xt, N * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
-                (e = hipMemcpyAsync(W.r, W.w, N * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
-                (e = hipMemcpyAsync(W.scal + 3, W.scal + 4, 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        if ((e = fetch(12)) != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
+        if (host[10] != 0.0 || host[11] != 0.0) {        // a step was taken
+            if ((e = hipMemcpyAsync(W.scal + 3, W.scal + 4, 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
                 return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
-            *beta = bt;
+            *beta = host[4];
             ++corrections;
         }
         return H2_OK;
@@ -486,7 +525,7 @@ struct Solver {
             if (*relres <= tol) return H2_OK;
             if (*mv >= max_mv) return H2_NOT_CONVERGED;
             if (precond == 3) {
-                h2_status st = restart_correction(prec, rhs, x, &beta, mv);
+                h2_status st = restart_correction(prec, x, &beta, mv);
                 if (st != H2_OK) return st;
                 *relres = beta / bnorm;
                 if (*relres <= tol) return H2_OK;

@@ -28,7 +28,7 @@ constexpr int kTile = 16;         // basis vectors per dot-product pass
 constexpr int kHs = 128;          // per-column stride of hcol, cs, sn, y
 constexpr int kGs = 136;          // per-column stride of g
 constexpr int kSs = 8;            // per-column stride of the scalars: 0 ||w||, 1 |g_{j+1}|, 2 ||b||, 3 ||r||,
-                                  // 4 trial residual, 5 ||w|| before orthogonalisation
+                                  // 5 ||w|| before orthogonalisation, 6-7 step of the restart correction
 constexpr double kDgks = 0.70710678118654752;   // repeat Gram-Schmidt when the norm drops below this fraction
 
 __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {   // conj(a) * b
@@ -221,22 +221,7 @@ __global__ void kb_reduce_add(double2* __restrict__ a, const double2* __restrict
     a[(int64_t)c * kHs + i].y += b[(int64_t)c * kHs + i].y;
 }
 
-// out_c = a_c + b_c
-__global__ void kb_sum(const double2* __restrict__ a, const double2* __restrict__ b, double2* __restrict__ out,
-                       int64_t ld, int64_t N) {
-    const int c = blockIdx.z;
-    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
-        out[c * ld + n] = make_double2(a[c * ld + n].x + b[c * ld + n].x, a[c * ld + n].y + b[c * ld + n].y);
-}
 
-// dst_c = src_c where take[c]
-__global__ void kb_select(double2* __restrict__ dst, const double2* __restrict__ src, int64_t ld, int64_t N,
-                          const int* __restrict__ take) {
-    const int c = blockIdx.z;
-    if (!take[c]) return;
-    for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < N; n += int64_t(gridDim.x) * blockDim.x)
-        dst[c * ld + n] = src[c * ld + n];
-}
 
 __global__ void kb_givens(double2* __restrict__ H, int64_t hs, int ldh, int j, const double2* __restrict__ hcol,
                           double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
@@ -262,9 +247,57 @@ __global__ void kb_init_g(double2* __restrict__ g, int m, const double* __restri
         g[(int64_t)c * kGs + i] = make_double2(i == 0 ? scal[c * kSs + slot] : 0.0, 0.0);
 }
 
+// Restart correction, per column: scal[c][6..7] = alpha_c = w^H r / ||w||^2 from the dot
+// (dots[c]) and the partial norms of w; 0 for a column that is not open, when ||w|| = 0,
+// or when alpha is not a number.
+__global__ void kb_mr_alpha(const double* __restrict__ npart, int nblk, const double2* __restrict__ dots,
+                            double* __restrict__ scal, const int* __restrict__ open) {
+    const int c = blockIdx.x;
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += npart[(int64_t)c * nblk + b];
+    s = wsum(s);
+    if (threadIdx.x == 0) {
+        double ar = 0.0, ai = 0.0;
+        if (open[c] && s > 0.0) {
+            ar = dots[(int64_t)c * kHs].x / s;
+            ai = dots[(int64_t)c * kHs].y / s;
+            if (!isfinite(ar) || !isfinite(ai)) ar = ai = 0.0;
+        }
+        scal[c * kSs + 6] = ar;
+        scal[c * kSs + 7] = ai;
+    }
+}
+
+// d_c += alpha_c c_c, r_c -= alpha_c w_c; partial squared norms of the new r_c
+__global__ __launch_bounds__(256) void kb_mr_step(double2* __restrict__ d, const double2* __restrict__ cv,
+                                                  double2* __restrict__ r, const double2* __restrict__ w, int64_t ld,
+                                                  int64_t N, const double* __restrict__ scal,
+                                                  double* __restrict__ npart) {
+    __shared__ double red[4];
+    const int c = blockIdx.z;
+    const double ar = scal[c * kSs + 6], ai = scal[c * kSs + 7];
+    double nn = 0;
+    for (int64_t n = blockIdx.x * 256 + threadIdx.x; n < N; n += int64_t(gridDim.x) * 256) {
+        const int64_t o = c * ld + n;
+        const double2 a = cv[o], wv = w[o];
+        double2 dv = d[o], rv = r[o];
+        dv.x += ar * a.x - ai * a.y;
+        dv.y += ar * a.y + ai * a.x;
+        rv.x -= ar * wv.x - ai * wv.y;
+        rv.y -= ar * wv.y + ai * wv.x;
+        d[o] = dv;
+        r[o] = rv;
+        nn += rv.x * rv.x + rv.y * rv.y;
+    }
+    nn = wsum(nn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+    __syncthreads();
+    if (threadIdx.x == 0) npart[(int64_t)c * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 struct BWork {
     double2 *V, *Zs;                 // bases [j][c][ld]
-    double2 *W, *Rin, *R, *D, *Zx, *Dt;   // columns [c][ld]
+    double2 *W, *Rin, *R, *D, *Zx;   // columns [c][ld]
     float2 *lo_in, *lo_out;
     double2 *hcol, *H, *sn, *g, *y, *dpart;
     double *cs, *scal, *npart;
@@ -287,7 +320,6 @@ size_t bwork_layout(int64_t ld, int ncol, int m, int nblk, BWork* W, char* base,
     BWork w{};
     w.V = (double2*)take(col * (m + 1) * 16);
     w.Zs = precond ? (double2*)take(col * m * 16) : nullptr;
-    w.Dt = precond == 3 ? (double2*)take(col * 16) : nullptr;
     if (precond >= 2) {
         w.mX = (float*)take(size_t(nleaf) * n_in * 4);
         w.mH1 = (float*)take(size_t(nleaf) * n_hidden * 4);
@@ -392,10 +424,11 @@ struct BSolver {
         return e == hipSuccess ? H2_OK : handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
     }
 
-    // Learned correction at a cycle start, per open column: d_c + P(r_c) replaces d_c
-    // (and the residual r_c) when it lowers ||rhs_c - Z d_c||.
-    h2_status restart_correction(int prec, const double2* rhs, double2* dsol, std::vector<double>& res,
-                                 const std::vector<char>& open, std::vector<int>& mv, int* spent) {
+    // Learned correction at a cycle start, per open column: c = P(r_c), w = Z c and the
+    // minimal-residual step d_c += alpha_c c, r_c -= alpha_c w with alpha_c = w^H r_c / ||w||^2
+    // (none when w = 0); res follows r.
+    h2_status restart_correction(int prec, double2* dsol, std::vector<double>& res, const std::vector<char>& open,
+                                 std::vector<int>& mv, int* spent) {
         hipError_t e;
         for (int c = 0; c < ncol; ++c) {
             if (open[c])
@@ -404,27 +437,27 @@ struct BSolver {
                 e = hipMemsetAsync(W.W + c * ld, 0, size_t(N) * 16, s);
             if (e != hipSuccess) return handle_fail(H2_ERR_DEVICE, hipGetErrorString(e));
         }
-        kb_sum<<<cgrid(), 256, 0, s>>>(dsol, W.W, W.Dt, ld, N);
-        h2_status st = prod(prec, W.Dt, W.Zx);
+        h2_status st = prod(prec, W.W, W.Zx);
         if (st != H2_OK) return st;
         ++*spent;
-        kb_residual<<<cgrid(), 256, 0, s>>>(rhs, ld, W.Zx, ld, W.W, ld, N, W.npart);
-        kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 4);
+        std::vector<int> op(ncol, 0);
+        for (int c = 0; c < ncol; ++c) op[c] = open[c] ? 1 : 0;
+        if ((st = upload_ints(W.acc, op)) != H2_OK) return st;
+        kb_multidot<<<cgrid(), 256, 0, s>>>(W.Zx, ld, ld, 1, nullptr, W.Rin, ld, N, W.dpart);   // w^H r
+        kb_reduce<<<ncol, 128, 0, s>>>(W.dpart, nblk, 1, nullptr, W.y, 0);
+        kb_norm2<<<cgrid(), 256, 0, s>>>(W.Zx, ld, N, W.npart);                                 // ||w||^2
+        kb_mr_alpha<<<ncol, 64, 0, s>>>(W.npart, nblk, W.y, W.scal, W.acc);
+        kb_mr_step<<<cgrid(), 256, 0, s>>>(dsol, W.W, W.Rin, W.Zx, ld, N, W.scal, W.npart);
+        kb_finish_norm<<<ncol, 64, 0, s>>>(W.npart, nblk, W.scal, 3);
         if ((st = fetch()) != H2_OK) return st;
-        std::vector<int> take(ncol, 0);
         for (int c = 0; c < ncol; ++c) {
             if (!open[c]) continue;
             ++mv[c];
-            const double rt = host[c * kSs + 4];
-            if (std::isfinite(rt) && rt < res[c]) {
-                take[c] = 1;
-                res[c] = rt;
+            if (host[c * kSs + 6] != 0.0 || host[c * kSs + 7] != 0.0) {
                 ++corrections[c];
+                res[c] = host[c * kSs + 3];
             }
         }
-        if ((st = upload_ints(W.acc, take)) != H2_OK) return st;
-        kb_select<<<cgrid(), 256, 0, s>>>(dsol, W.Dt, ld, N, W.acc);
-        kb_select<<<cgrid(), 256, 0, s>>>(W.Rin, W.W, ld, N, W.acc);
         return H2_OK;
     }
     std::vector<int> corrections;
@@ -461,7 +494,7 @@ struct BSolver {
             }
             if (!any || spent >= max_mv) break;
             if (precond == 3) {
-                if ((st = restart_correction(prec, rhs, dsol, res, open, mv, &spent)) != H2_OK) return st;
+                if ((st = restart_correction(prec, dsol, res, open, mv, &spent)) != H2_OK) return st;
                 any = false;
                 for (int c = 0; c < ncol; ++c) {
                     open[c] = open[c] && res[c] > target[c];

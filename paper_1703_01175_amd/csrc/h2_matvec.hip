@@ -323,7 +323,7 @@ __device__ __forceinline__ int opaque_zero() {
 }
 
 // Owned columns [0, nown) of the row come first in its storage: column j's rows are
-// at S + j k_t, its coefficient row of X at src[j] (read one step ahead).
+// at S + j k_t, its coefficient row of X at src[j].
 template <typename TB, typename TV, int RL>
 __device__ __forceinline__ void coupling_sym_row(int kt, int nown, const TB* __restrict__ S,
                                                  const int* __restrict__ src, const TV* __restrict__ Xh,
@@ -343,53 +343,64 @@ __device__ __forceinline__ void coupling_sym_row(int kt, int nown, const TB* __r
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[q][c] = czero<TV>();
-    int jn = w * CG + cg;
-    int sn = jn < nown ? src[jn] : 0;
-    for (int j0 = w * CG; j0 < nown; j0 += 4 * CG) {
-        const int j = j0 + cg;
-        const bool live = j < nown;
-        const int sj = sn;
-        jn = j + 4 * CG;
-        sn = jn < nown ? src[jn] : 0;
-        const TB* col = S + (int64_t)(live ? j : 0) * kt;
-        TB sv[4];
+    constexpr int U = 2;                 // wave steps whose loads are issued together
+    for (int j0 = w * CG; j0 < nown; j0 += 4 * CG * U) {
+        int jj[U];
+        bool live[U];
+        TB sv[U][4];
+        TV xl[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = rl + RL * q;
-            if (live && r < kt) sv[q] = ldnt(col + r);
-            else { sv[q].x = 0; sv[q].y = 0; }
+        for (int u = 0; u < U; ++u) {
+            jj[u] = j0 + 4 * CG * u + cg;
+            live[u] = jj[u] < nown;
+            const TB* col = S + (int64_t)(live[u] ? jj[u] : 0) * kt;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = rl + RL * q;
+                if (live[u] && r < kt) sv[u][q] = ldnt(col + r);
+                else { sv[u][q].x = 0; sv[u][q].y = 0; }
+            }
         }
-        TV xs[3];
-        if constexpr (RL == 4) {         // lane rl < 3 fetches component rl; the quad shares it
-            const TV xl = (live && rl < 3) ? Xh[(int64_t)sj * kNcomp + rl] : czero<TV>();
-            xs[0] = quad_bcast<0>(xl);
-            xs[1] = quad_bcast<1>(xl);
-            xs[2] = quad_bcast<2>(xl);
-        } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) xs[c] = live ? Xh[(int64_t)sj * kNcomp + c] : czero<TV>();
+        for (int u = 0; u < U; ++u) {
+            const int sj = live[u] ? src[jj[u]] : 0;
+            if constexpr (RL == 4)       // lane rl < 3 fetches component rl; the quad shares it
+                xl[u] = (live[u] && rl < 3) ? Xh[(int64_t)sj * kNcomp + rl] : czero<TV>();
         }
-        const int z = opaque_zero();
-        TV p0 = czero<TV>(), p1 = czero<TV>(), p2 = czero<TV>();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int u = 0; u < U; ++u) {
+            TV xs[3];
+            if constexpr (RL == 4) {
+                xs[0] = quad_bcast<0>(xl[u]);
+                xs[1] = quad_bcast<1>(xl[u]);
+                xs[2] = quad_bcast<2>(xl[u]);
+            } else {
+                const int sj = live[u] ? src[jj[u]] : 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) cfma(acc[q][c], sv[q], xs[c]);
-            const TV* xr = red[rl + RL * q + z];
-            cfma(p0, sv[q], xr[0]);
-            cfma(p1, sv[q], xr[1]);
-            cfma(p2, sv[q], xr[2]);
+                for (int c = 0; c < 3; ++c) xs[c] = live[u] ? Xh[(int64_t)sj * kNcomp + c] : czero<TV>();
+            }
+            const int z = opaque_zero();     // each step reads the X_t rows afresh
+            TV p0 = czero<TV>(), p1 = czero<TV>(), p2 = czero<TV>();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cfma(acc[q][c], sv[u][q], xs[c]);
+                const TV* xr = red[rl + RL * q + z];
+                cfma(p0, sv[u][q], xr[0]);
+                cfma(p1, sv[u][q], xr[1]);
+                cfma(p2, sv[u][q], xr[2]);
+            }
+            p0 = col_sum<RL>(p0);
+            p1 = col_sum<RL>(p1);
+            p2 = col_sum<RL>(p2);
+            // lane rl = c stores component c of the column's partial (selects, no indexing)
+            TV o = p2;
+            o.x = rl == 1 ? p1.x : o.x;
+            o.y = rl == 1 ? p1.y : o.y;
+            o.x = rl == 0 ? p0.x : o.x;
+            o.y = rl == 0 ? p0.y : o.y;
+            if (live[u] && rl < 3) part[(int64_t)jj[u] * kNcomp + rl] = o;
         }
-        p0 = col_sum<RL>(p0);
-        p1 = col_sum<RL>(p1);
-        p2 = col_sum<RL>(p2);
-        // lane rl = c stores component c of the column's partial (selects, no indexing)
-        TV o = p2;
-        o.x = rl == 1 ? p1.x : o.x;
-        o.y = rl == 1 ? p1.y : o.y;
-        o.x = rl == 0 ? p0.x : o.x;
-        o.y = rl == 0 ? p0.y : o.y;
-        if (live && rl < 3) part[(int64_t)j * kNcomp + rl] = o;
     }
     // Y_t rows: sum over the column groups of each 16-lane row, the 4 rows of the wave
     // and the 4 waves

@@ -120,9 +120,12 @@ def test_givens_rotation():
 
 
 def test_restart_correction_special_cases():
-    """correct = exact inverse: one accepted correction solves the system with no
-    Arnoldi step; correct = 0 (never accepted) is plain GMRES step for step;
-    a harmful correction is rejected every cycle and changes nothing but the count."""
+    """The restart correction is the minimal-residual step along c = correct(r):
+    x += alpha c with alpha = (A c)^H r / ||A c||^2.  correct = exact inverse: alpha = 1
+    and the system is solved with no Arnoldi step; correct = 0 (A c = 0): no step, plain
+    GMRES step for step; a c whose image is orthogonal to r: alpha = 0, no step; c = r
+    (any multiple): the step of the minimal-residual method, whose residual is checked
+    against its closed form; the residual never grows."""
     rng = np.random.default_rng(3)
     n = 60
     A = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
@@ -134,9 +137,22 @@ def test_restart_correction_special_cases():
     x1, r1 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: 0 * r)
     assert r1.corrections == 0 and r1.iterations == r0.iterations and r1.matvecs == r0.matvecs + r0.restarts
     assert np.allclose(x1, x0, rtol=0, atol=1e-12)
-    x2, r2 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=lambda r: -3.0 * r)
-    assert r2.corrections == 0 and r2.iterations == r0.iterations
+
+    def orthogonal(r):               # A c = q with q orthogonal to r
+        q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        q -= (np.vdot(r, q) / np.vdot(r, r)) * r
+        return Ainv @ q
+    x2, r2 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, correct=orthogonal)
+    assert r2.iterations == r0.iterations
     assert np.linalg.norm(b - A @ x2) <= 1e-10 * np.linalg.norm(b)
+    # one minimal-residual step along r from x = 0: r1 = b - alpha A b with
+    # alpha = (A b)^H b / ||A b||^2, so ||r1||^2 = ||b||^2 - |(A b)^H b|^2 / ||A b||^2
+    Ab = A @ b
+    closed = np.sqrt(np.linalg.norm(b) ** 2 - abs(np.vdot(Ab, b)) ** 2 / np.linalg.norm(Ab) ** 2)
+    x3, r3 = krylov.gmres(lambda v: A @ v, b, tol=1e-10, restart=8, max_matvec=1, correct=lambda r: -3.0 * r)
+    assert r3.corrections == 1 and r3.iterations == 0
+    assert abs(np.linalg.norm(b - A @ x3) - closed) <= 1e-12 * np.linalg.norm(b)
+    assert closed < np.linalg.norm(b)
 
 
 def test_bicgstab_against_scipy_iterations():
