@@ -390,11 +390,13 @@ h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* availab
  * the library stream each unordered pair once: the owning cluster adds
  * S_ts X_s to its coefficients and writes S_ts^T X_t for the other, which adds
  * those partials before the backward transformation.  This halves the coupling
- * stream; results agree with the full mode to rounding.
+ * stream; results agree with the full mode to rounding.  Handles start in the
+ * full mode: on MI355X the symmetric kernel, whose transposed products need a
+ * butterfly sum per column, takes as long for half the bytes as the full kernel
+ * for all of them.
  *   set: -1 query only, 0 every ordered block, 1 the symmetric mode
  *   *mode, *available: as for h2_near_mode (either may be NULL).
- * Handles start in the symmetric mode when it is available.  The multi-RHS
- * products and the BF16x3 tier stream every block.
+ * The multi-RHS products and the BF16x3 tier stream every block.
  * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 when the
  * mode is not available. */
 h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);

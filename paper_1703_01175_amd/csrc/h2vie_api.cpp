@@ -857,7 +857,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.row_off = (const int64_t*)(base + P.o_rowoff);
     if (P.csym) {
         D.coup_sym_ok = true;
-        D.coup_sym = true;
+        D.coup_sym = false;               // measured no faster than streaming every block
         D.row_nown = (const int*)(base + P.o_csym[0]);
         D.row_pbase = (const int*)(base + P.o_csym[1]);
         D.crecv_ptr = (const int*)(base + P.o_csym[2]);

@@ -112,7 +112,7 @@ def test_cube64_streamed_near_and_symmetric_couplings(full, capsys):
     ds = symmetrize_couplings(d)
     Hs = H2Operator(ds, tiers=("fp64",), keep_all_near=True, device="cuda:0")
     st = Hs.stats()
-    assert st["near_stored_elems"] == st["near_elems"] and Hs.coupling_mode() == (True, True)
+    assert st["near_stored_elems"] == st["near_elems"] and Hs.coupling_mode() == (False, True)
     x = h2gen.random_vector(3 * g.n_vox, 3)
     yo = om.h2_matvec(ds, x)
     xd = torch.from_numpy(x).cuda()
