@@ -274,6 +274,9 @@ typedef struct {
     int64_t coupling_owned_elems;  /* coupling entries streamed per product in the symmetric
                                       coupling mode (0: mode not available) */
     int64_t coupling_owned_cols;   /* their columns (one partial of 3 complex each) */
+    int64_t near_tiles;            /* tiles of the tiled near field (0: not available) */
+    int64_t near_tile_steps;       /* their steps: one stored block each, applied to up to 16
+                                      target leaves at once */
 } h2_stats_t;
 
 h2_status h2_stats(h2_handle h, h2_stats_t* out);
@@ -400,6 +403,23 @@ h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* availab
  * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 when the
  * mode is not available. */
 h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);
+
+/* Tiled near field of the FP64 single-vector product in the full near mode,
+ * available when identical near blocks are stored once (the default on uniform
+ * voxel grids; Sec. IV.B's near-field block products, unchanged).  Leaves
+ * consecutive in tree order form tiles of 16; a tile applies each stored block
+ * that its leaves use to all of their sources at once, on the FP64 matrix cores
+ * (16 x 16 x 4 products; the block is read once per tile instead of once per
+ * leaf pair).  Results agree with the per-leaf kernel to rounding (the products
+ * are summed in another order).
+ *   set: -1 query only, 0 the per-leaf kernel, 1 the tiled kernel
+ *   *on: 1 if FP64 full-mode products use the tiles after the call;
+ *   *available: 1 if the handle has tiles (either output may be NULL).
+ * Handles with tiles start with them on.  The symmetric near mode, the FP32 and
+ * BF16x3 tiers and the multi-RHS products do not use them.
+ * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 without
+ * tiles. */
+h2_status h2_near_tiles(h2_handle h, int32_t set, int32_t* on, int32_t* available);
 
 /* Diagnostics: with enable = 1, later products on h bracket every kernel
  * family with HIP events on the stream it runs on (the product's stream, or the

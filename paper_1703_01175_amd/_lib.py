@@ -68,7 +68,8 @@ class Stats(C.Structure):
                 ("coef_rows", C.c_int64), ("max_rank", C.c_int32), ("min_leaf_rank", C.c_int32),
                 ("dev_bytes", C.c_int64), ("bytes_fp64", C.c_double), ("flops_fp64", C.c_double),
                 ("near_stored_elems", C.c_int64), ("near_unique", C.c_int64), ("near_passes", C.c_int64),
-                ("coupling_owned_elems", C.c_int64), ("coupling_owned_cols", C.c_int64)]
+                ("coupling_owned_elems", C.c_int64), ("coupling_owned_cols", C.c_int64),
+                ("near_tiles", C.c_int64), ("near_tile_steps", C.c_int64)]
 
 
 _LIB = None
@@ -131,6 +132,8 @@ def load() -> C.CDLL:
     lib.h2_near_mode.restype = C.c_int
     lib.h2_near_mode.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.h2_coupling_mode.restype = C.c_int
+    lib.h2_near_tiles.restype = C.c_int
+    lib.h2_near_tiles.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.h2_coupling_mode.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     pd = C.POINTER(MlpDims)
     for name, args in [

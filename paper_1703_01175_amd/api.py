@@ -213,6 +213,13 @@ class H2Operator:
         self.mlp = mlp
 
     # ------------------------------------------------------------------ misc
+    def near_tiles(self, on: bool | None = None) -> tuple[bool, bool]:
+        """(tiled near field in use, tiles available); on=True/False selects it."""
+        cur, avail = C.c_int32(0), C.c_int32(0)
+        _lib.check(self.lib.h2_near_tiles(self.handle, -1 if on is None else int(bool(on)),
+                                          C.byref(cur), C.byref(avail)))
+        return bool(cur.value), bool(avail.value)
+
     def near_mode(self, symmetric: bool | None = None) -> tuple[bool, bool]:
         """(symmetric mode in use, symmetric mode available); symmetric=True/False selects it."""
         mode, avail = C.c_int32(0), C.c_int32(0)

@@ -9,6 +9,7 @@ namespace h2 {
 
 constexpr int kNcomp = 3;        // field components per voxel
 constexpr int kMaxLeaf = 64;     // voxels per leaf cluster
+constexpr int kTileLeaves = 16;  // target leaves per tile of the tiled near field
 constexpr int kMrRhs = 4;        // right-hand sides per pass of the multi-RHS FP64 / FP32 product
 constexpr int kMrCols = kNcomp * kMrRhs;
 constexpr int kMaxRank = 256;    // cluster rank limit
@@ -98,6 +99,18 @@ struct DevH2 {
     // stream runs the upward pass, the couplings and the downward pass (unset: in order)
     hipStream_t near_side = nullptr;
     hipEvent_t near_fork = nullptr, near_join = nullptr;
+    // tiled near field (FP64, stored-once blocks, full mode): tiles of kTileLeaves target
+    // leaves; step q of a tile is one stored block and, per target slot, the tree position
+    // of the source leaf it multiplies (-1: none)
+    bool near_tiles_ok = false;         // the plan has tiles (blocks stored once)
+    bool near_tiles = false;            // FP64 full-mode products use them
+    int n_tiles = 0;
+    const int* tile_ptr = nullptr;      // [n_tiles + 1] into the step list
+    const int* tile_leaf = nullptr;     // [n_tiles][kTileLeaves] target leaves (-1: none)
+    const int64_t* step_off = nullptr;  // per step: complex offset of its stored block
+    const int* step_shape = nullptr;    // per step: rows | columns << 16
+    const int* step_src = nullptr;      // [steps][kTileLeaves] source tree positions (-1: none)
+    const void* tile_zero = nullptr;    // [kMaxLeaf][3] zeros (FP64): the source of an empty slot
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
     bool near_sym = false;              // products use it (selectable while near_sym_ok)

@@ -12,6 +12,8 @@
 // vector/accumulation type TV (double2 for FP64, float2 for FP32).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "h2_internal.h"
 
 namespace h2 {
@@ -606,6 +608,139 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
     }
 }
 
+// ---------------------------------------------------------------- tiled near field on the matrix cores
+// Full-mode near field over stored-once blocks, FP64: a group takes a tile of up to
+// kTileLeaves target leaves and walks the tile's steps; a step is one stored block G
+// (n_t x n_s, column-major) and, for each target slot j, the source leaf whose U_s it
+// multiplies (or none).  G is read once per step for all the tile's targets instead of
+// once per leaf pair.  Products are v_mfma_f64_16x16x4f64: A = 16 rows x 4 columns of
+// G, B = 4 rows of U_s x 16 target slots, one 16 x 16 tile per field component; the
+// complex product takes four real ones (re += Gr Ur - Gi Ui, im += Gr Ui + Gi Ur).
+// Operand layouts: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result
+// register r of lane l is row 4 r + l / 16, column l % 16.  Waves w and w + 4 own rows
+// 16 (w & 3) .. + 15 and take alternate steps; their sums meet in LDS, then every
+// target's rows are finished as in k_near_epilogue.
+// part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
+// 2: both in one launch.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One k step's operands: 4 columns of G (16 rows a wave) and the matching 4 rows of
+// the 16 sources, for the three field components.
+struct TileOps {
+    double2 a, u0, u1, u2;
+};
+
+__device__ __forceinline__ TileOps tile_load(const double2* __restrict__ gp, const double2* __restrict__ up,
+                                            const double2* __restrict__ zero, int nt, int ns, int k0, int kq) {
+    // columns past n_s take their G entry from the zero block (the address is chosen
+    // before the load, so nothing waits for the loaded value until its use) and read
+    // row 0 of the source
+    const int k = k0 + kq;
+    const bool ok = k < ns;
+    TileOps o;
+    o.a = *(ok ? gp + (int64_t)k * nt : zero);
+    const double2* u = up + (ok ? k : 0) * kNcomp;
+    o.u0 = u[0];
+    o.u1 = u[1];
+    o.u2 = u[2];
+    return o;
+}
+
+__device__ __forceinline__ void tile_mma(const TileOps& o, v4d& re0, v4d& im0, v4d& re1, v4d& im1, v4d& re2,
+                                         v4d& im2) {
+    const double nai = -o.a.y;
+    re0 = mfma64(o.a.x, o.u0.x, re0);
+    im0 = mfma64(o.a.x, o.u0.y, im0);
+    re1 = mfma64(o.a.x, o.u1.x, re1);
+    im1 = mfma64(o.a.x, o.u1.y, im1);
+    re2 = mfma64(o.a.x, o.u2.x, re2);
+    im2 = mfma64(o.a.x, o.u2.y, im2);
+    re0 = mfma64(nai, o.u0.y, re0);
+    im0 = mfma64(o.a.y, o.u0.x, im0);
+    re1 = mfma64(nai, o.u1.y, re1);
+    im1 = mfma64(o.a.y, o.u1.x, im1);
+    re2 = mfma64(nai, o.u2.y, re2);
+    im2 = mfma64(o.a.y, o.u2.x, im2);
+}
+
+__global__ __launch_bounds__(512) void k_near_tile(
+    int part, const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf,
+    const int64_t* __restrict__ step_off, const int* __restrict__ step_shape, const int* __restrict__ step_src,
+    const double2* __restrict__ near, const double2* __restrict__ zsrc, double2* __restrict__ ypart,
+    const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
+    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const double2* __restrict__ basis,
+    const double2* __restrict__ U, const double2* __restrict__ Yh, const int* __restrict__ perm,
+    const double2* __restrict__ x, double2* __restrict__ y, int op, double alpha) {
+    __shared__ double2 red[kMaxLeaf][kTileLeaves][kNcomp];
+    const int tile = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rl = lane & 15, kq = lane >> 4;
+    const int row = 16 * (w & 3) + rl;
+    v4d re0 = {0, 0, 0, 0}, re1 = re0, re2 = re0, im0 = re0, im1 = re0, im2 = re0;
+    if (part != 1) {
+        const int e = tile_ptr[tile + 1];
+        for (int st = tile_ptr[tile] + (w >> 2); st < e; st += 2) {
+            const int shape = step_shape[st];
+            const int nt = shape & 0xffff, ns = shape >> 16;
+            const int sb = step_src[(int64_t)st * kTileLeaves + rl];
+            // rows past n_t only reach rows that are never finished, so they read row 0;
+            // a slot without a source reads a block of zeros
+            const double2* gp = near + step_off[st] + (row < nt ? row : 0);
+            const double2* up = sb >= 0 ? U + (int64_t)sb * kNcomp : zsrc;
+            // two k steps in flight: each register set is reloaded right after its use,
+            // so no loaded register is copied (a copy would wait for its load)
+            TileOps p = tile_load(gp, up, zsrc, nt, ns, 0, kq);
+            TileOps q = tile_load(gp, up, zsrc, nt, ns, 4, kq);
+            // (the scheduling barriers keep each reload where it is written: left alone,
+            // the scheduler sinks every load to just before its use)
+            for (int k0 = 0; k0 < ns; k0 += 8) {
+                tile_mma(p, re0, im0, re1, im1, re2, im2);
+                p = tile_load(gp, up, zsrc, nt, ns, k0 + 8, kq);
+                __builtin_amdgcn_sched_barrier(0);
+                tile_mma(q, re0, im0, re1, im1, re2, im2);
+                q = tile_load(gp, up, zsrc, nt, ns, k0 + 12, kq);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    // the two halves' sums meet in LDS: red[row][slot][component]
+    const int r0 = 16 * (w & 3) + kq;
+    if (w >= 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            red[r0 + 4 * r][rl][0] = make_double2(re0[r], im0[r]);
+            red[r0 + 4 * r][rl][1] = make_double2(re1[r], im1[r]);
+            red[r0 + 4 * r][rl][2] = make_double2(re2[r], im2[r]);
+        }
+    }
+    __syncthreads();
+    if (w < 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = r0 + 4 * r;
+            red[i][rl][0] = cadd(red[i][rl][0], make_double2(re0[r], im0[r]));
+            red[i][rl][1] = cadd(red[i][rl][1], make_double2(re1[r], im1[r]));
+            red[i][rl][2] = cadd(red[i][rl][2], make_double2(re2[r], im2[r]));
+        }
+    }
+    __syncthreads();
+    const int pass = part == 1 ? 1 : 0, npass = part == 2 ? 1 : 2;
+    for (int j = w; j < kTileLeaves; j += 8) {
+        const int t = tile_leaf[tile * kTileLeaves + j];
+        if (t < 0) continue;
+        const int n = cl_size[t];
+        if (lane < n)
+            near_finish_row<double2, double2>(t, n, lane, red[lane][j][0], red[lane][j][1], red[lane][j][2], pass,
+                                              npass, ypart, cl_rank, cl_coef, cl_begin, cl_basis_off, basis, Yh,
+                                              perm, x, y, op, alpha);
+    }
+}
+
 // ---------------------------------------------------------------- symmetric near field
 // Sum over the 16 lanes of each DPP row (rotations by 8, 4, 2, 1): every lane of
 // the row ends with the row's sum.  All 64 lanes must be active.
@@ -820,7 +955,15 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     // full mode over stored-once blocks: all passes but the last read only U, so they
     // run on the side stream beside the upward pass, couplings and downward pass (when
     // the kernel families are timed, those passes are timed on the side stream)
-    const bool overlap = !d.near_sym && d.near_passes > 1 && d.near_side;
+    constexpr bool fp64 = std::is_same<TV, double2>::value && std::is_same<TB, double2>::value;
+    const bool tiles = fp64 && d.near_tiles && !d.near_sym;
+    const bool overlap = !d.near_sym && d.near_side && (tiles || d.near_passes > 1);
+    auto near_tile = [&](int part, const TV* xr, TV* yr, hipStream_t st) {
+        if constexpr (fp64)
+            k_near_tile<<<d.n_tiles, 512, 0, st>>>(part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src,
+                                                   near, (const double2*)d.tile_zero, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin,
+                                                   d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
+    };
     auto near_kernel = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
     auto near_pass = [&](int pass, const TV* xr, TV* yr, hipStream_t st) {
         const int np = d.near_passes;
@@ -840,7 +983,10 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             if (e == hipSuccess) e = hipStreamWaitEvent(d.near_side, d.near_fork, 0);
             if (e != hipSuccess) return e;
             if (prof) prof->begin(5, d.near_side);
-            for (int pass = 0; pass + 1 < d.near_passes; ++pass) near_pass(pass, xr, yr, d.near_side);
+            if (tiles)
+                near_tile(0, xr, yr, d.near_side);
+            else
+                for (int pass = 0; pass + 1 < d.near_passes; ++pass) near_pass(pass, xr, yr, d.near_side);
             if (prof) prof->end(5, d.near_side);
             if ((e = hipEventRecord(d.near_join, d.near_side)) != hipSuccess) return e;
         }
@@ -895,6 +1041,9 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                                                                 d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis,
                                                                 Yh, d.perm, xr, yr, op, alpha);
             end(6);
+        } else if (tiles) {
+            near_tile(overlap ? 1 : 2, xr, yr, s);
+            end(5);
         } else if (overlap) {
             near_pass(d.near_passes - 1, xr, yr, s);
             end(5);

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/h2vie.h"
@@ -67,6 +68,13 @@ struct Plan {
     int near_passes = 1;
     std::vector<int> near_pass_ptr;
     size_t o_npass = 0, o_ypart = 0;
+    // tiled near field over stored-once blocks (see DevH2): tiles of kTileLeaves leaves
+    // consecutive in tree order, each with its steps (one stored block, per target slot a
+    // source); every tile walks the stored blocks in the same order
+    std::vector<int> tile_ptr, tile_leaf, step_shape, step_src;
+    std::vector<int64_t> step_off;
+    int64_t tile_pairs = 0;
+    size_t o_tile[4] = {0, 0, 0, 0}, o_stepoff = 0, o_tzero = 0;
     // symmetric near field: each unordered leaf pair once (empty when G_st != G_ts^T somewhere)
     bool sym = false;
     int64_t sym_pairs = 0;
@@ -477,6 +485,50 @@ void plan_symmetric_couplings(const h2_host_desc* d, const std::vector<int64_t>&
     P.csym = true;
 }
 
+// Tiles for the tiled near field: kTileLeaves leaves consecutive in tree order (the
+// tree's leaves follow its spatial bisection, so a tile is a compact brick) and, per
+// tile, one step per stored block that any of its leaves uses (a second step where a
+// leaf uses the same stored block twice), in ascending storage order.
+static void plan_near_tiles(const h2_host_desc* d, const std::vector<int64_t>& nfirst,
+                            const std::vector<int64_t>& ncount, Plan& P) {
+    P.tile_ptr.clear(); P.tile_leaf.clear(); P.step_shape.clear(); P.step_src.clear(); P.step_off.clear();
+    P.tile_pairs = 0;
+    if (!P.near_dedup) return;
+    std::vector<int> leaves;
+    for (int c = 0; c < d->n_clusters; ++c)
+        if (d->nchild[c] == 0) leaves.push_back(c);
+    std::stable_sort(leaves.begin(), leaves.end(), [&](int a, int b) { return d->begin[a] < d->begin[b]; });
+    P.tile_ptr.push_back(0);
+    for (size_t t0 = 0; t0 < leaves.size(); t0 += kTileLeaves) {
+        // (stored offset, rows, columns) -> per slot, the sources' tree positions
+        std::map<std::tuple<int64_t, int, int>, std::vector<std::vector<int>>> steps;
+        for (int j = 0; j < kTileLeaves; ++j) {
+            const int t = t0 + j < leaves.size() ? leaves[t0 + j] : -1;
+            P.tile_leaf.push_back(t);
+            if (t < 0) continue;
+            const int nt = int(d->end[t] - d->begin[t]);
+            for (int64_t i = nfirst[t]; i < nfirst[t] + ncount[t]; ++i) {
+                const int s = d->near_s[i];
+                auto& v = steps[std::make_tuple(P.near_uoff[i], nt, int(d->end[s] - d->begin[s]))];
+                if (v.empty()) v.resize(kTileLeaves);
+                v[j].push_back(int(d->begin[s]));
+                P.tile_pairs++;
+            }
+        }
+        for (auto& kv : steps) {
+            size_t reps = 0;
+            for (auto& v : kv.second) reps = std::max(reps, v.size());
+            for (size_t r = 0; r < reps; ++r) {
+                P.step_off.push_back(std::get<0>(kv.first));
+                P.step_shape.push_back(std::get<1>(kv.first) | (std::get<2>(kv.first) << 16));
+                for (int j = 0; j < kTileLeaves; ++j)
+                    P.step_src.push_back(r < kv.second[j].size() ? kv.second[j][r] : -1);
+            }
+        }
+        P.tile_ptr.push_back(int(P.step_off.size()));
+    }
+}
+
 h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     h2_status st = validate(d);
     if (st != H2_OK) return st;
@@ -560,6 +612,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     }
 
     plan_symmetric_near(d, nfirst, ncount, P);
+    plan_near_tiles(d, nfirst, ncount, P);
 
     // leaves in cluster order with their diagonal near block (per-leaf preconditioners)
     for (int c = 0; c < nc; ++c) {
@@ -637,7 +690,13 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
     P.o_noff = L.add(i64s(P.near_off.size()));
     P.o_npass = L.add(ints(P.near_pass_ptr.size()));
 
-    if (P.near_passes > 1) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
+    if (!P.tile_ptr.empty()) {
+        const std::vector<int>* tv[4] = {&P.tile_ptr, &P.tile_leaf, &P.step_shape, &P.step_src};
+        for (int q = 0; q < 4; ++q) P.o_tile[q] = L.add(ints(tv[q]->size()));
+        P.o_stepoff = L.add(i64s(P.step_off.size()));
+        P.o_tzero = L.add(size_t(kMaxLeaf) * kNcomp * 16);
+    }
+    if (P.near_passes > 1 || !P.tile_ptr.empty()) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
     P.o_rowcl = L.add(ints(P.row_cl.size()));
     P.o_rownc = L.add(ints(P.row_ncols.size()));
     P.o_rowcp = L.add(ints(P.row_colptr.size()));
@@ -753,6 +812,13 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     errs.push_back(put(P.o_nss, P.near_ssize.data(), P.near_ssize.size() * 4));
     errs.push_back(put(P.o_noff, P.near_off.data(), P.near_off.size() * 8));
     errs.push_back(put(P.o_npass, P.near_pass_ptr.data(), P.near_pass_ptr.size() * 4));
+    if (!P.tile_ptr.empty()) {
+        const std::vector<int>* tv[4] = {&P.tile_ptr, &P.tile_leaf, &P.step_shape, &P.step_src};
+        for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_tile[q], tv[q]->data(), tv[q]->size() * 4));
+        errs.push_back(put(P.o_stepoff, P.step_off.data(), P.step_off.size() * 8));
+        const std::vector<double> zeros(size_t(kMaxLeaf) * kNcomp * 2, 0.0);
+        errs.push_back(put(P.o_tzero, zeros.data(), zeros.size() * 8));
+    }
 
     errs.push_back(put(P.o_rowcl, P.row_cl.data(), P.row_cl.size() * 4));
     errs.push_back(put(P.o_rownc, P.row_ncols.data(), P.row_ncols.size() * 4));
@@ -877,8 +943,19 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.near_passes = P.near_passes;
     D.near_pass_ptr = (const int*)(base + P.o_npass);
 
-    D.near_ypart = P.near_passes > 1 ? base + P.o_ypart : nullptr;
-    if (P.near_passes > 1) {   // side stream (default priority) for the passes that need only U
+    D.near_ypart = P.near_passes > 1 || !P.tile_ptr.empty() ? base + P.o_ypart : nullptr;
+    if (!P.tile_ptr.empty()) {
+        D.near_tiles_ok = true;
+        D.near_tiles = true;
+        D.n_tiles = int(P.tile_ptr.size()) - 1;
+        D.tile_ptr = (const int*)(base + P.o_tile[0]);
+        D.tile_leaf = (const int*)(base + P.o_tile[1]);
+        D.step_shape = (const int*)(base + P.o_tile[2]);
+        D.step_src = (const int*)(base + P.o_tile[3]);
+        D.step_off = (const int64_t*)(base + P.o_stepoff);
+        D.tile_zero = base + P.o_tzero;
+    }
+    if (P.near_passes > 1 || !P.tile_ptr.empty()) {   // side stream (default priority) for near work that needs only U
         hipStream_t side = nullptr;
         hipEvent_t ef = nullptr, ej = nullptr;
         if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
@@ -971,6 +1048,8 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     S.near_stored_elems = P.near_stored_len;
     S.near_unique = P.near_dedup ? int64_t(P.near_src.size()) : d->n_near;
     S.near_passes = D.near_passes;
+    S.near_tiles = D.n_tiles;
+    S.near_tile_steps = int64_t(P.step_off.size());
     S.coupling_owned_elems = P.csym ? P.csym_elems : 0;
     S.coupling_owned_cols = P.csym ? P.csym_cols : 0;
     S.coupling_elems = d->coupling_len;
@@ -1050,6 +1129,17 @@ h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* availab
     if (set >= 0) h->dev.near_sym = set == 1;
     if (mode) *mode = h->dev.near_sym ? 1 : 0;
     if (available) *available = h->dev.near_sym_ok ? 1 : 0;
+    return H2_OK;
+}
+
+h2_status h2_near_tiles(h2_handle h, int32_t set, int32_t* on, int32_t* available) {
+    if (!handle_ok(h)) return fail(H2_ERR_BAD_HANDLE, "invalid handle");
+    if (set < -1 || set > 1) return fail(H2_ERR_INVALID_ARG, "near tiles setting must be -1, 0 or 1");
+    if (set == 1 && !h->dev.near_tiles_ok)
+        return fail(H2_ERR_INVALID_ARG, "near blocks are not stored once: no tiled near field");
+    if (set >= 0) h->dev.near_tiles = set == 1;
+    if (on) *on = h->dev.near_tiles ? 1 : 0;
+    if (available) *available = h->dev.near_tiles_ok ? 1 : 0;
     return H2_OK;
 }
 

@@ -89,7 +89,9 @@ def test_plan_stores_identical_near_blocks_once():
     st, n = _plan(d)
     st2, n2 = _plan(d, flags=1)
     assert st == 0 and st2 == 0
-    assert n2 - n >= 16 * (d.near.size - stored) - 4096
+    # (the stored-once plan adds the near-field tiles: steps of 16 source slots, and
+    # the row sums of the side-stream launch)
+    assert n2 - n >= 16 * (d.near.size - stored) - 48 * d.n_vox - (1 << 18)
     assert _plan(d, flags=2)[0] == -1
 
 

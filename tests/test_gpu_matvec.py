@@ -127,7 +127,8 @@ def test_profile_counts_kernel_families(torch):
     launches = np.frombuffer(bytes(buf)[64:], np.int64)
     # with several near passes over stored-once blocks, the early passes run (and are
     # timed) on the side stream: two near intervals per product
-    per = 2 if (H.stats()["near_passes"] > 1 and not H.near_mode()[0]) else 1
+    # (so does the tiled near field, whose block products run there before the finish)
+    per = 2 if ((H.stats()["near_passes"] > 1 or H.near_tiles()[0]) and not H.near_mode()[0]) else 1
     assert launches[5] == 3 * per and launches[0] == 3 and ms[5] > 0
     assert lib.h2_profile_enable(H.handle, 0) == 0
 
@@ -231,14 +232,54 @@ def test_overlapped_near_passes_over_several_rhs(torch):
     X = h2gen.random_vector(3 * g.n_vox, 41, ncols=3)               # (3, N)
     lib = H.lib
     Xd = torch.from_numpy(X).cuda()
-    Yd = torch.empty_like(Xd)
     import ctypes as C
     from paper_1703_01175_amd import _lib
-    _lib.check(lib.h2_matvec(H.handle, 1, 0, C.c_void_p(Xd.data_ptr()), C.c_void_p(Yd.data_ptr()), 3, H.N, None))
-    Y = Yd.cpu().numpy()
-    for c in range(3):
-        assert _rel(Y[c], om.h2_matvec(d, X[c])) <= 1e-12, c
+    for tiles in (False, True):          # the passes, then the tiled near field
+        assert H.near_tiles(tiles) == (tiles, True)
+        Yd = torch.empty_like(Xd)
+        _lib.check(lib.h2_matvec(H.handle, 1, 0, C.c_void_p(Xd.data_ptr()), C.c_void_p(Yd.data_ptr()), 3, H.N, None))
+        Y = Yd.cpu().numpy()
+        for c in range(3):
+            assert _rel(Y[c], om.h2_matvec(d, X[c])) <= 1e-12, (tiles, c)
     H.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tiled_near_field_matches_per_leaf_kernel_and_oracle(torch, name):
+    """Near blocks stored once: the FP64 full-mode product applies each stored block
+    to the sources of 16 target leaves at once on the matrix cores (tiles of 16 leaves
+    consecutive in tree order).  It covers leaves of 27 voxels (cube12: columns past a
+    block's width, rows past its height), tiles with empty slots (cube8: 8 leaves) and
+    every geometry here; the products match the per-leaf kernel to rounding and the
+    oracle, for Z and G.  Without stored-once blocks there are no tiles."""
+    from paper_1703_01175_amd._lib import H2Error
+    print(f"[gpu] tiled near field {name}", flush=True)
+    g, d, H = operator(name)
+    st = H.stats()
+    stored_once = st["near_stored_elems"] < st["near_elems"]
+    n_leaves = int(st["n_leaves"])
+    if not stored_once:
+        assert H.near_tiles() == (False, False) and st["near_tiles"] == 0
+        with pytest.raises(H2Error):
+            H.near_tiles(True)
+        return
+    assert st["near_tiles"] == (n_leaves + 15) // 16
+    assert st["near_tile_steps"] >= st["n_near"] / 16
+    sym0 = H.near_mode()[0]
+    H.near_mode(False)
+    assert H.near_tiles() == (True, True)
+    x = h2gen.random_vector(3 * g.n_vox, 43)
+    xs = torch.from_numpy(x).cuda()
+    for op in ("Z", "G"):
+        yt = H.matvec(xs, op=op).cpu().numpy()
+        assert H.near_tiles(False) == (False, True)
+        yl = H.matvec(xs, op=op).cpu().numpy()
+        assert H.near_tiles(True) == (True, True)
+        yo = om.h2_matvec(d, x, op)
+        assert _rel(yt, yl) <= 1e-13, op
+        assert _rel(yt, yo) <= 1e-12, op
+        assert np.abs(yt - yo).max() <= 1e-12 * np.abs(yo).max(), op
+    H.near_mode(sym0)
 
 
 SYM_CASES = ["cube12_sym", "rod_sym", "slab_sym", "cube13_sym", "box9_sym", "cube16_sym"]
