@@ -104,6 +104,7 @@ struct DevH2 {
     // of the source leaf it multiplies (-1: none)
     bool near_tiles_ok = false;         // the plan has tiles (blocks stored once)
     bool near_tiles = false;            // FP64 full-mode products use them
+    bool tiles_full = false;            // every step is a kMaxLeaf x kMaxLeaf block
     int n_tiles = 0;
     const int* tile_ptr = nullptr;      // [n_tiles + 1] into the step list
     const int* tile_leaf = nullptr;     // [n_tiles][kTileLeaves] target leaves (-1: none)
@@ -111,6 +112,7 @@ struct DevH2 {
     const int* step_shape = nullptr;    // per step: rows | columns << 16
     const int* step_src = nullptr;      // [steps][kTileLeaves] source tree positions (-1: none)
     const void* tile_zero = nullptr;    // [kMaxLeaf][3] zeros (FP64): the source of an empty slot
+    void* tile_part1 = nullptr;         // [n_vox][3] tree order: the second split group's sums (FP64)
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T
     bool near_sym = false;              // products use it (selectable while near_sym_ok)

@@ -615,7 +615,10 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 // multiplies (or none).  G is read once per step for all the tile's targets instead of
 // once per leaf pair.  Products are v_mfma_f64_16x16x4f64: A = 16 rows x 4 columns of
 // G, B = 4 rows of U_s x 16 target slots, one 16 x 16 tile per field component; the
-// complex product takes four real ones (re += Gr Ur - Gi Ui, im += Gr Ui + Gi Ur).
+// complex product takes four real ones (re += Gr Ur - Gi Ui, im += Gr Ui + Gi Ur) or,
+// in the 3M form, three (see tile_mma).  This kernel takes any block shape (leaves of
+// fewer than 64 voxels); tiles whose steps are all full 64 x 64 blocks use
+// k_near_tile_split below.
 // Operand layouts: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result
 // register r of lane l is row 4 r + l / 16, column l % 16.  Waves w and w + 4 own rows
 // 16 (w & 3) .. + 15 and take alternate steps; their sums meet in LDS, then every
@@ -623,6 +626,9 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 // part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
 // 2: both in one launch.
 typedef double v4d __attribute__((ext_vector_type(4)));
+// complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur + Ui))
+// instead of four
+constexpr bool kTile3M = true;
 
 __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -650,23 +656,36 @@ __device__ __forceinline__ TileOps tile_load(const double2* __restrict__ gp, con
     return o;
 }
 
-__device__ __forceinline__ void tile_mma(const TileOps& o, v4d& re0, v4d& im0, v4d& re1, v4d& im1, v4d& re2,
-                                         v4d& im2) {
-    const double nai = -o.a.y;
-    re0 = mfma64(o.a.x, o.u0.x, re0);
-    im0 = mfma64(o.a.x, o.u0.y, im0);
-    re1 = mfma64(o.a.x, o.u1.x, re1);
-    im1 = mfma64(o.a.x, o.u1.y, im1);
-    re2 = mfma64(o.a.x, o.u2.x, re2);
-    im2 = mfma64(o.a.x, o.u2.y, im2);
-    re0 = mfma64(nai, o.u0.y, re0);
-    im0 = mfma64(o.a.y, o.u0.x, im0);
-    re1 = mfma64(nai, o.u1.y, re1);
-    im1 = mfma64(o.a.y, o.u1.x, im1);
-    re2 = mfma64(nai, o.u2.y, re2);
-    im2 = mfma64(o.a.y, o.u2.x, im2);
+// acc[c][q], component c: with four real products q = 0 re, 1 im; with three (M3,
+// the 3M form) q = 0 Gr Ur, 1 Gi Ui, 2 (Gr + Gi)(Ur + Ui), so re = [0] - [1] and
+// im = [2] - [0] - [1]
+template <bool M3>
+__device__ __forceinline__ void tile_mma(const TileOps& o, v4d (&acc)[3][3]) {
+    const double2 u[3] = {o.u0, o.u1, o.u2};
+    if constexpr (M3) {
+        const double sa = o.a.x + o.a.y;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c][0] = mfma64(o.a.x, u[c].x, acc[c][0]);
+            acc[c][1] = mfma64(o.a.y, u[c].y, acc[c][1]);
+            acc[c][2] = mfma64(sa, u[c].x + u[c].y, acc[c][2]);
+        }
+    } else {
+        const double nai = -o.a.y;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c][0] = mfma64(o.a.x, u[c].x, acc[c][0]);
+            acc[c][1] = mfma64(o.a.x, u[c].y, acc[c][1]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c][0] = mfma64(nai, u[c].y, acc[c][0]);
+            acc[c][1] = mfma64(o.a.y, u[c].x, acc[c][1]);
+        }
+    }
 }
 
+template <bool M3>
 __global__ __launch_bounds__(512) void k_near_tile(
     int part, const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf,
     const int64_t* __restrict__ step_off, const int* __restrict__ step_shape, const int* __restrict__ step_src,
@@ -681,7 +700,11 @@ __global__ __launch_bounds__(512) void k_near_tile(
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rl = lane & 15, kq = lane >> 4;
     const int row = 16 * (w & 3) + rl;
-    v4d re0 = {0, 0, 0, 0}, re1 = re0, re2 = re0, im0 = re0, im1 = re0, im2 = re0;
+    v4d acc[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[c][q] = v4d{0, 0, 0, 0};
     if (part != 1) {
         const int e = tile_ptr[tile + 1];
         for (int st = tile_ptr[tile] + (w >> 2); st < e; st += 2) {
@@ -699,34 +722,36 @@ __global__ __launch_bounds__(512) void k_near_tile(
             // (the scheduling barriers keep each reload where it is written: left alone,
             // the scheduler sinks every load to just before its use)
             for (int k0 = 0; k0 < ns; k0 += 8) {
-                tile_mma(p, re0, im0, re1, im1, re2, im2);
+                tile_mma<M3>(p, acc);
                 p = tile_load(gp, up, zsrc, nt, ns, k0 + 8, kq);
                 __builtin_amdgcn_sched_barrier(0);
-                tile_mma(q, re0, im0, re1, im1, re2, im2);
+                tile_mma<M3>(q, acc);
                 q = tile_load(gp, up, zsrc, nt, ns, k0 + 12, kq);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
     // the two halves' sums meet in LDS: red[row][slot][component]
+    double2 v[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            v[c][r] = M3 ? make_double2(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
+                         : make_double2(acc[c][0][r], acc[c][1][r]);
     const int r0 = 16 * (w & 3) + kq;
     if (w >= 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            red[r0 + 4 * r][rl][0] = make_double2(re0[r], im0[r]);
-            red[r0 + 4 * r][rl][1] = make_double2(re1[r], im1[r]);
-            red[r0 + 4 * r][rl][2] = make_double2(re2[r], im2[r]);
-        }
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red[r0 + 4 * r][rl][c] = v[c][r];
     }
     __syncthreads();
     if (w < 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = r0 + 4 * r;
-            red[i][rl][0] = cadd(red[i][rl][0], make_double2(re0[r], im0[r]));
-            red[i][rl][1] = cadd(red[i][rl][1], make_double2(re1[r], im1[r]));
-            red[i][rl][2] = cadd(red[i][rl][2], make_double2(re2[r], im2[r]));
-        }
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red[r0 + 4 * r][rl][c] = cadd(red[r0 + 4 * r][rl][c], v[c][r]);
     }
     __syncthreads();
     const int pass = part == 1 ? 1 : 0, npass = part == 2 ? 1 : 2;
@@ -739,6 +764,139 @@ __global__ __launch_bounds__(512) void k_near_tile(
                                               npass, ypart, cl_rank, cl_coef, cl_begin, cl_basis_off, basis, Yh,
                                               perm, x, y, op, alpha);
     }
+}
+
+// Split form for full blocks: two groups of four waves per tile, taking alternate
+// steps, so that a CU holds two groups whose step boundaries (two barriers each: the
+// buffer's reads done, then its refill) fall at different times and one keeps the
+// matrix cores busy while the other refills.  Wave w owns rows 16 w .. + 15 and all 64
+// columns of the block; the group's sources are staged in one LDS buffer; the A
+// operand runs two k steps ahead across steps.  Group h leaves its sums in part[h]
+// (tree order); k_near_tile_finish adds the two and finishes the rows.
+template <bool M3>
+__global__ __launch_bounds__(256) void k_near_tile_split(
+    const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf, const int64_t* __restrict__ step_off,
+    const int* __restrict__ step_src, const double2* __restrict__ near, const double2* __restrict__ zsrc,
+    const int* __restrict__ cl_begin, const int* __restrict__ cl_size, const double2* __restrict__ U,
+    double2* __restrict__ part0, double2* __restrict__ part1) {
+    constexpr int kSlice = kMaxLeaf * kNcomp;
+    constexpr int kChunks = kTileLeaves * kSlice / 256;        // entries each thread stages per step
+    constexpr int kSteps = kMaxLeaf / 4;                       // k steps of 4 columns
+    constexpr int kRowStride = kTileLeaves * kNcomp;
+    __shared__ double2 stage[kMaxLeaf][kTileLeaves][kNcomp];
+    const int tile = blockIdx.x >> 1, h = blockIdx.x & 1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rl = lane & 15, kq = lane >> 4;
+    const int row = 16 * w + rl;
+    v4d acc[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[c][q] = v4d{0, 0, 0, 0};
+    const int b = tile_ptr[tile] + h, e = tile_ptr[tile + 1];
+    if (b < e) {
+        int sb[kChunks];
+        double2 sv[kChunks];
+        auto srcs = [&](int st) {
+#pragma unroll
+            for (int j = 0; j < kChunks; ++j) sb[j] = step_src[(int64_t)st * kTileLeaves + (tid + 256 * j) / kSlice];
+        };
+        auto fetch = [&]() {
+#pragma unroll
+            for (int j = 0; j < kChunks; ++j)
+                sv[j] = *(sb[j] >= 0 ? U + (int64_t)sb[j] * kNcomp + (tid + 256 * j) % kSlice : zsrc);
+        };
+        auto store = [&]() {
+#pragma unroll
+            for (int j = 0; j < kChunks; ++j) {
+                const int i = tid + 256 * j;
+                const int n = i / kSlice, o = i % kSlice;
+                double2 v = sv[j];
+                asm volatile("" : "+v"(v.x), "+v"(v.y));
+                stage[o / kNcomp][n][o % kNcomp] = v;
+            }
+        };
+        const int mine = b + ((e - 1 - b) >> 1) * 2;              // this group's last step
+        auto last = [&](int st) { return st < e ? st : mine; };   // past the end: re-read the last
+        auto aptr = [&](int st) { return near + step_off[st] + row + (int64_t)kq * kMaxLeaf; };
+        srcs(b);
+        fetch();
+        store();
+        srcs(last(b + 2));
+        const double2* ga = aptr(b);
+        double2 a0 = ga[0], a1 = ga[4 * kMaxLeaf];
+        __syncthreads();
+        for (int st = b; st < e; st += 2) {
+            fetch();                                            // slices of step st + 2
+            srcs(last(st + 4));
+            const double2* gn = aptr(last(st + 2));
+            const double2* bs = &stage[0][0][0] + (kq * kTileLeaves + rl) * kNcomp;
+            double2 bu[2][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bu[0][c] = bs[c];
+#pragma unroll
+            for (int i = 0; i < kSteps; ++i) {
+                if (i + 1 < kSteps) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) bu[(i + 1) & 1][c] = bs[(i + 1) * 4 * kRowStride + c];
+                }
+                TileOps o;
+                o.a = (i & 1) ? a1 : a0;
+                o.u0 = bu[i & 1][0];
+                o.u1 = bu[i & 1][1];
+                o.u2 = bu[i & 1][2];
+                tile_mma<M3>(o, acc);
+                const double2* src = i + 2 < kSteps ? ga + (i + 2) * 4 * kMaxLeaf : gn + (i + 2 - kSteps) * 4 * kMaxLeaf;
+                if (i & 1)
+                    a1 = *src;
+                else
+                    a0 = *src;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            ga = gn;
+            __syncthreads();                                    // every wave is done with the buffer
+            store();
+            __syncthreads();
+        }
+    }
+    // sums to this group's partial buffer: register r of lane l is row 4 r + l / 16 of
+    // the wave's 16, slot l % 16
+    double2* out = h ? part1 : part0;
+    const int t = tile_leaf[tile * kTileLeaves + rl];
+    if (t >= 0) {
+        const int n = cl_size[t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + 4 * r + kq;
+            if (i < n) {
+                double2* o = out + (int64_t)(cl_begin[t] + i) * kNcomp;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    o[c] = M3 ? make_double2(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
+                              : make_double2(acc[c][0][r], acc[c][1][r]);
+            }
+        }
+    }
+}
+
+// The rows of leaf slot blockIdx.x: the two split groups' sums, the leaf backward
+// transformation and the epilogue (as k_near_epilogue's last pass).
+__global__ __launch_bounds__(64) void k_near_tile_finish(
+    const int* __restrict__ leaf_id, const double2* __restrict__ part0, const double2* __restrict__ part1,
+    const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
+    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const double2* __restrict__ basis,
+    const double2* __restrict__ Yh, const int* __restrict__ perm, const double2* __restrict__ x,
+    double2* __restrict__ y, int op, double alpha) {
+    const int t = leaf_id[blockIdx.x];
+    const int n = cl_size[t];
+    const int lane = threadIdx.x;
+    if (lane >= n) return;
+    const int64_t i = (int64_t)(cl_begin[t] + lane) * kNcomp;
+    near_finish_row<double2, double2>(t, n, lane, cadd(part0[i], part1[i]), cadd(part0[i + 1], part1[i + 1]),
+                                      cadd(part0[i + 2], part1[i + 2]), 0, 1, nullptr, cl_rank, cl_coef, cl_begin,
+                                      cl_basis_off, basis, Yh, perm, x, y, op, alpha);
 }
 
 // ---------------------------------------------------------------- symmetric near field
@@ -959,10 +1117,23 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     const bool tiles = fp64 && d.near_tiles && !d.near_sym;
     const bool overlap = !d.near_sym && d.near_side && (tiles || d.near_passes > 1);
     auto near_tile = [&](int part, const TV* xr, TV* yr, hipStream_t st) {
-        if constexpr (fp64)
-            k_near_tile<<<d.n_tiles, 512, 0, st>>>(part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src,
-                                                   near, (const double2*)d.tile_zero, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin,
-                                                   d.cl_size, d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
+        if constexpr (fp64) {
+            if (d.tiles_full) {
+                if (part != 1)
+                    k_near_tile_split<kTile3M><<<2 * d.n_tiles, 256, 0, st>>>(
+                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const double2*)d.tile_zero, d.cl_begin,
+                        d.cl_size, U, (double2*)d.near_ypart, (double2*)d.tile_part1);
+                if (part != 0)
+                    k_near_tile_finish<<<d.n_leaves, 64, 0, st>>>(
+                        d.leaf_id, (const double2*)d.near_ypart, (const double2*)d.tile_part1, d.cl_rank, d.cl_coef,
+                        d.cl_begin, d.cl_size, d.cl_basis_off, basis, Yh, d.perm, xr, yr, op, alpha);
+            } else {
+                k_near_tile<kTile3M><<<d.n_tiles, 512, 0, st>>>(
+                    part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near,
+                    (const double2*)d.tile_zero, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
+                    d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
+            }
+        }
     };
     auto near_kernel = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
     auto near_pass = [&](int pass, const TV* xr, TV* yr, hipStream_t st) {

@@ -74,7 +74,7 @@ struct Plan {
     std::vector<int> tile_ptr, tile_leaf, step_shape, step_src;
     std::vector<int64_t> step_off;
     int64_t tile_pairs = 0;
-    size_t o_tile[4] = {0, 0, 0, 0}, o_stepoff = 0, o_tzero = 0;
+    size_t o_tile[4] = {0, 0, 0, 0}, o_stepoff = 0, o_tzero = 0, o_tpart1 = 0;
     // symmetric near field: each unordered leaf pair once (empty when G_st != G_ts^T somewhere)
     bool sym = false;
     int64_t sym_pairs = 0;
@@ -695,6 +695,7 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         for (int q = 0; q < 4; ++q) P.o_tile[q] = L.add(ints(tv[q]->size()));
         P.o_stepoff = L.add(i64s(P.step_off.size()));
         P.o_tzero = L.add(size_t(kMaxLeaf) * kNcomp * 16);
+        P.o_tpart1 = L.add(size_t(n) * kNcomp * 16);
     }
     if (P.near_passes > 1 || !P.tile_ptr.empty()) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
     P.o_rowcl = L.add(ints(P.row_cl.size()));
@@ -953,7 +954,10 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         D.step_shape = (const int*)(base + P.o_tile[2]);
         D.step_src = (const int*)(base + P.o_tile[3]);
         D.step_off = (const int64_t*)(base + P.o_stepoff);
+        D.tiles_full = std::all_of(P.step_shape.begin(), P.step_shape.end(),
+                                   [](int sh) { return sh == (kMaxLeaf | (kMaxLeaf << 16)); });
         D.tile_zero = base + P.o_tzero;
+        D.tile_part1 = base + P.o_tpart1;
     }
     if (P.near_passes > 1 || !P.tile_ptr.empty()) {   // side stream (default priority) for near work that needs only U
         hipStream_t side = nullptr;
