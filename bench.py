@@ -378,7 +378,11 @@ def product_leg(H, d, x, y, steps, warmup, workload):
         nb -= 16.0 * (streamed - st["near_stored_elems"])
         product_bytes -= 16.0 * (streamed - st["near_stored_elems"])
     tiles = (not sym) and H.near_tiles()[0]
-    near_kernel = "k_near_sym" if sym else ("k_near_tile" if tiles else "k_near_epilogue")
+    # tiles of full 64 x 64 blocks (every leaf 64 voxels) run the split kernel
+    leaf = np.asarray(d.nchild) == 0
+    tiles_full = bool(np.all((np.asarray(d.end) - np.asarray(d.begin))[leaf] == 64))
+    near_kernel = "k_near_sym" if sym else (("k_near_tile_split" if tiles_full else "k_near_tile") if tiles
+                                            else "k_near_epilogue")
     # near-kernel dispatches per product (the tiled kernel: the block products, then a
     # launch that only finishes the rows; both are timed as one interval each)
     near_launches = 1 if (sym or tiles) else int(st["near_passes"])
@@ -433,8 +437,9 @@ def product_leg(H, d, x, y, steps, warmup, workload):
                     "traffic": measured_traffic(workload, near_kernel),
                     "flops_per_launch": near_flops, "avg_ms": round(float(near_ms), 4), "launches_per_product": 1,
                     "note": "identical near blocks stored once, applied to 16 target leaves at a time on the FP64 "
-                            "matrix cores (dense FP64 MFMA peak); time of the block-product launch and the "
-                            "row-finishing launch together"}
+                            "matrix cores (dense FP64 MFMA peak; 8 real flops per complex multiply-add, of which "
+                            "the 3M form executes 6); time of the block-product launch and the row-finishing "
+                            "launch together, beside the coupling phase"}
     else:
         tf = near_flops / (near_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": near_kernel, "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
