@@ -72,6 +72,7 @@ struct DevH2 {
 
     // coupling launch (row clusters, most work first)
     const int* row_cl = nullptr;        // [n_rowcl]
+    bool coupling_mr_mfma = false;      // ranks <= 64: multi-RHS FP64 couplings on the matrix cores
     const int* row_ncols = nullptr;     // grouped columns sum(k_s)
     const int64_t* row_off = nullptr;   // complex offset of the grouped block row
     const int* row_colptr = nullptr;    // first entry in colsrc
@@ -102,6 +103,7 @@ struct DevH2 {
     // tiled near field (FP64, stored-once blocks, full mode): tiles of kTileLeaves target
     // leaves; step q of a tile is one stored block and, per target slot, the tree position
     // of the source leaf it multiplies (-1: none)
+    const void* zero_block = nullptr;   // [kMaxLeaf][3] zeros (FP64): read in place of absent operands
     bool near_tiles_ok = false;         // the plan has tiles (blocks stored once)
     bool near_tiles = false;            // FP64 full-mode products use them
     bool tiles_full = false;            // every step is a kMaxLeaf x kMaxLeaf block
@@ -111,7 +113,6 @@ struct DevH2 {
     const int64_t* step_off = nullptr;  // per step: complex offset of its stored block
     const int* step_shape = nullptr;    // per step: rows | columns << 16
     const int* step_src = nullptr;      // [steps][kTileLeaves] source tree positions (-1: none)
-    const void* tile_zero = nullptr;    // [kMaxLeaf][3] zeros (FP64): the source of an empty slot
     void* tile_part1 = nullptr;         // [n_vox][3] tree order: the second split group's sums (FP64)
     // symmetric near field (each unordered leaf pair streamed once; see the plan)
     bool near_sym_ok = false;           // the description's near blocks satisfy G_st = G_ts^T

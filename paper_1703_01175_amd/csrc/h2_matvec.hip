@@ -1121,7 +1121,7 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             if (d.tiles_full) {
                 if (part != 1)
                     k_near_tile_split<kTile3M><<<2 * d.n_tiles, 256, 0, st>>>(
-                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const double2*)d.tile_zero, d.cl_begin,
+                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const double2*)d.zero_block, d.cl_begin,
                         d.cl_size, U, (double2*)d.near_ypart, (double2*)d.tile_part1);
                 if (part != 0)
                     k_near_tile_finish<<<d.n_leaves, 64, 0, st>>>(
@@ -1130,7 +1130,7 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             } else {
                 k_near_tile<kTile3M><<<d.n_tiles, 512, 0, st>>>(
                     part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near,
-                    (const double2*)d.tile_zero, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
+                    (const double2*)d.zero_block, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
                     d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
             }
         }

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "h2_internal.h"
 
@@ -187,6 +188,131 @@ __device__ __forceinline__ void coupling_mr_rows(int kt, int ncols, const TB* __
     }
 }
 
+// FP64: the grouped row on the matrix cores (v_mfma_f64_16x16x4f64, complex products
+// in the 3M form).  One group of four waves per row slot; wave w takes k steps w, w + 4,
+// ... of 4 grouped columns each.  A = RT tiles of 16 rows x the step's 4 columns of S
+// (lane l: row l % 16, column l / 16); B = the 4 columns' gathered coefficient rows x 16
+// (lane l: column l / 16, right-hand-side column l % 16, zero past kMrCols).  Operands
+// run two steps ahead, the gather indices three, each from a register ring reloaded
+// right after its use; columns past the row's end read a zero entry instead of
+// branching.  The four waves' sums meet in LDS (fixed order).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int RT>
+__device__ __forceinline__ void coupling_mr_mfma_rows(int kt, int ncols, const double2* __restrict__ S,
+                                                      const int* __restrict__ src, const double2* __restrict__ Xh,
+                                                      const double2* __restrict__ zero, double2* __restrict__ Yh,
+                                                      int co, double2 (*red)[kMaxLeaf][16]) {
+    constexpr int D = 2;                     // k steps of loads in flight per wave
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int rl = lane & 15, kq = lane >> 4;
+    const int nsteps = (ncols + 3) >> 2;
+    v4d acc[RT][3];
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[u][q] = v4d{0, 0, 0, 0};
+    struct Ops {
+        double2 a[RT];
+        double2 b;
+    };
+    // gather index of this lane's column in step i of this wave (its first column if past the end)
+    auto gidx = [&](int i) {
+        const int j = 4 * (w + 4 * i) + kq;
+        return src[j < ncols ? j : 0];
+    };
+    auto load = [&](int i, int g) {
+        const int j = 4 * (w + 4 * i) + kq;
+        const bool ok = j < ncols;
+        Ops o;
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            const int r = 16 * u + rl;
+            o.a[u] = *(ok && r < kt ? S + (int64_t)j * kt + r : zero);
+        }
+        o.b = *(ok && rl < C ? Xh + (int64_t)g * C + rl : zero);
+        return o;
+    };
+    auto mma = [&](const Ops& o) {
+        const double sb = o.b.x + o.b.y;
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            acc[u][0] = mfma64(o.a[u].x, o.b.x, acc[u][0]);
+            acc[u][1] = mfma64(o.a[u].y, o.b.y, acc[u][1]);
+            acc[u][2] = mfma64(o.a[u].x + o.a[u].y, sb, acc[u][2]);
+        }
+    };
+    const int mine = nsteps > w ? (nsteps - 1 - w) / 4 + 1 : 0;      // this wave's steps
+    if (mine > 0) {
+        // ring of D steps' operands and gather indices: slot u holds step i + u; each is
+        // reloaded (D steps ahead) right after its use, past the end with zeros
+        Ops ops[D];
+        int g[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) g[u] = gidx(u);
+#pragma unroll
+        for (int u = 0; u < D; ++u) ops[u] = load(u, g[u]);
+#pragma unroll
+        for (int u = 0; u < D; ++u) g[u] = gidx(u + D);
+        for (int i = 0; i < mine; i += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                mma(ops[u]);
+                ops[u] = load(i + u + D, g[u]);
+                g[u] = gidx(i + u + 2 * D);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    // register r of lane l in tile u: row 16 u + 4 r + l / 16, column l % 16
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[w][16 * u + 4 * r + kq][rl] =
+                make_double2(acc[u][0][r] - acc[u][1][r], acc[u][2][r] - acc[u][0][r] - acc[u][1][r]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kt * C; e += 256) {
+        const int r = e / C, c = e % C;
+        double2 sum = red[0][r][c];
+        sum = mr_add(sum, red[1][r][c]);
+        sum = mr_add(sum, red[2][r][c]);
+        sum = mr_add(sum, red[3][r][c]);
+        Yh[(int64_t)(co + r) * C + c] = sum;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_coupling_mr_mfma(const int* __restrict__ row_cl,
+                                                          const int* __restrict__ row_ncols,
+                                                          const int64_t* __restrict__ row_off,
+                                                          const int* __restrict__ row_colptr,
+                                                          const int* __restrict__ colsrc,
+                                                          const int* __restrict__ cl_rank,
+                                                          const int* __restrict__ cl_coef,
+                                                          const double2* __restrict__ coupling,
+                                                          const double2* __restrict__ zero,
+                                                          const double2* __restrict__ Xh, double2* __restrict__ Yh) {
+    __shared__ double2 red[4][kMaxLeaf][16];
+    const int slot = blockIdx.x;
+    const int t = row_cl[slot];
+    const int kt = cl_rank[t];
+    const int ncols = row_ncols[slot];
+    const double2* S = coupling + row_off[slot];
+    const int* src = colsrc + row_colptr[slot];
+    const int co = cl_coef[t];
+    if (kt <= 16)
+        coupling_mr_mfma_rows<1>(kt, ncols, S, src, Xh, zero, Yh, co, red);
+    else if (kt <= 32)
+        coupling_mr_mfma_rows<2>(kt, ncols, S, src, Xh, zero, Yh, co, red);
+    else
+        coupling_mr_mfma_rows<4>(kt, ncols, S, src, Xh, zero, Yh, co, red);
+}
+
 template <typename TB, typename TV>
 __global__ __launch_bounds__(256) void k_coupling_mr(const int* __restrict__ row_cl, const int* __restrict__ row_ncols,
                                                      const int64_t* __restrict__ row_off,
@@ -330,8 +456,19 @@ hipError_t mr_tier(const DevH2& d, const LevelLaunch& lv, int op, const TierData
                     k_transfer_up_mr<TB, TV><<<lv.up_count[l], 256, 0, s>>>(d.up_list + lv.up_begin[l], d.cl_rank,
                                                                             d.cl_coef, d.cl_first_child, d.cl_nchild,
                                                                             d.cl_transfer_off, transfer, Xh);
-            k_coupling_mr<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr, d.colsrc,
-                                                            d.cl_rank, d.cl_coef, coupling, Xh, Yh);
+            // FP64 with ranks up to 64: on the matrix cores
+            bool done = false;
+            if constexpr (std::is_same<TV, double2>::value && std::is_same<TB, double2>::value) {
+                if (d.coupling_mr_mfma) {
+                    k_coupling_mr_mfma<<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr,
+                                                                 d.colsrc, d.cl_rank, d.cl_coef, coupling,
+                                                                 (const double2*)d.zero_block, Xh, Yh);
+                    done = true;
+                }
+            }
+            if (!done)
+                k_coupling_mr<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_ncols, d.row_off, d.row_colptr,
+                                                                d.colsrc, d.cl_rank, d.cl_coef, coupling, Xh, Yh);
             for (int l = 0; l < lv.n_down; ++l)
                 if (lv.down_count[l] > 0)
                     k_transfer_down_mr<TB, TV><<<lv.down_count[l], 256, 0, s>>>(d.down_list + lv.down_begin[l],

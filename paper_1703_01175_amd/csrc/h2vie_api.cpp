@@ -83,6 +83,7 @@ struct Plan {
     size_t o_sym[7] = {0, 0, 0, 0, 0, 0, 0}, o_symoff = 0, o_sympart = 0, o_symrows = 0;
     std::vector<int> row_cl, row_ncols, row_colptr, colsrc;
     std::vector<int64_t> row_off;
+
     // symmetric couplings (empty when S_st != S_ts^T somewhere): each unordered admissible
     // pair streamed once by its owner; per row slot the owned columns (their storage
     // column in the grouped row and coefficient row), their first partial column, and the
@@ -694,9 +695,9 @@ h2_status make_plan(const h2_host_desc* d, const h2_build_opts* o, Plan& P) {
         const std::vector<int>* tv[4] = {&P.tile_ptr, &P.tile_leaf, &P.step_shape, &P.step_src};
         for (int q = 0; q < 4; ++q) P.o_tile[q] = L.add(ints(tv[q]->size()));
         P.o_stepoff = L.add(i64s(P.step_off.size()));
-        P.o_tzero = L.add(size_t(kMaxLeaf) * kNcomp * 16);
         P.o_tpart1 = L.add(size_t(n) * kNcomp * 16);
     }
+    P.o_tzero = L.add(size_t(kMaxLeaf) * kNcomp * 16);
     if (P.near_passes > 1 || !P.tile_ptr.empty()) P.o_ypart = L.add(size_t(n) * kNcomp * 16);
     P.o_rowcl = L.add(ints(P.row_cl.size()));
     P.o_rownc = L.add(ints(P.row_ncols.size()));
@@ -817,9 +818,9 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         const std::vector<int>* tv[4] = {&P.tile_ptr, &P.tile_leaf, &P.step_shape, &P.step_src};
         for (int q = 0; q < 4; ++q) errs.push_back(put(P.o_tile[q], tv[q]->data(), tv[q]->size() * 4));
         errs.push_back(put(P.o_stepoff, P.step_off.data(), P.step_off.size() * 8));
-        const std::vector<double> zeros(size_t(kMaxLeaf) * kNcomp * 2, 0.0);
-        errs.push_back(put(P.o_tzero, zeros.data(), zeros.size() * 8));
     }
+    const std::vector<double> zeros(size_t(kMaxLeaf) * kNcomp * 2, 0.0);
+    errs.push_back(put(P.o_tzero, zeros.data(), zeros.size() * 8));
 
     errs.push_back(put(P.o_rowcl, P.row_cl.data(), P.row_cl.size() * 4));
     errs.push_back(put(P.o_rownc, P.row_ncols.data(), P.row_ncols.size() * 4));
@@ -897,6 +898,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.n_leaves = int(P.leaf_id.size());
     D.coef_rows = P.coef_rows;
     D.n_rowcl = int(P.row_cl.size());
+    D.coupling_mr_mfma = P.max_rank <= 64;
     D.depth = P.depth;
     D.k = d->k;
     D.volume = d->volume;
@@ -944,6 +946,7 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
     D.near_passes = P.near_passes;
     D.near_pass_ptr = (const int*)(base + P.o_npass);
 
+    D.zero_block = base + P.o_tzero;
     D.near_ypart = P.near_passes > 1 || !P.tile_ptr.empty() ? base + P.o_ypart : nullptr;
     if (!P.tile_ptr.empty()) {
         D.near_tiles_ok = true;
@@ -956,7 +959,6 @@ h2_status h2_build_from_host(const h2_host_desc* d, const h2_build_opts* o, void
         D.step_off = (const int64_t*)(base + P.o_stepoff);
         D.tiles_full = std::all_of(P.step_shape.begin(), P.step_shape.end(),
                                    [](int sh) { return sh == (kMaxLeaf | (kMaxLeaf << 16)); });
-        D.tile_zero = base + P.o_tzero;
         D.tile_part1 = base + P.o_tpart1;
     }
     if (P.near_passes > 1 || !P.tile_ptr.empty()) {   // side stream (default priority) for near work that needs only U
