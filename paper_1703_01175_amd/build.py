@@ -36,15 +36,24 @@ def compile_flags():
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-I", os.path.join(HERE, "..", "include")]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    objdir = os.path.join(HERE, "_build")
+# host code only: AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# built as usual); used by the CPU tests of the host-side validation and planning
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+ASAN_LIB = os.path.join(LIBDIR, "asan", "libh2vie.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    lib = ASAN_LIB if sanitize else LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    objdir = os.path.join(HERE, "_build_asan" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    extra = SANITIZE_FLAGS if sanitize else []
 
     def one(src):
         obj = os.path.join(objdir, src + ".o")
-        cmd = [cc, *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *compile_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,13 +65,15 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = lib + ".tmp"
+    link_extra = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-shared-libsan"] if sanitize else []
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

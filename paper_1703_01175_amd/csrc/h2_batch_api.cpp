@@ -11,6 +11,7 @@
 #include <mutex>
 #include <set>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/h2vie.h"
@@ -244,6 +245,12 @@ static void group_phases(h2_group g) {
     }
     const int nph = 3 + g->n_up + g->n_down;
     g->host.assign(nph, GPhase());
+    // p + off as integer arithmetic: the sizing passes build the same tables before
+    // any buffer exists, and offsetting a null pointer is undefined
+    auto at = [](auto* p, int64_t off) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + uintptr_t(off) * sizeof(T));
+    };
     auto rel_phase = [&](int mi, const RelPhase& R, GPhase& G) {
         BatchHost* B = g->members[mi].B;
         const int64_t cols = B->max_cols;
@@ -254,10 +261,10 @@ static void group_phases(h2_group g) {
         const int tbase = int(G.terms.size());
         for (const RelTerm& t : R.terms) {
             BTerm T{};
-            T.a = B->arena + t.a;
+            T.a = at(B->arena, t.a);
             T.bld = brows(t.b_kind);
             T.bps = T.bld * cols;
-            T.b = bbase(t.b_kind) + t.b_row;
+            T.b = at(bbase(t.b_kind), t.b_row);
             T.kp = t.kp;
             G.terms.push_back(T);
         }
@@ -265,7 +272,7 @@ static void group_phases(h2_group g) {
             BOwner O{};
             O.ld = orows(o.out_kind);
             O.ps = O.ld * cols;
-            O.out = obase(o.out_kind) + o.out_row;
+            O.out = at(obase(o.out_kind), o.out_row);
             O.mp = o.mp;
             O.t0 = tbase + o.t0;
             O.nt = o.nt;
