@@ -415,8 +415,8 @@ def product_leg(H, d, x, y, steps, warmup, workload):
              "frac": round(product_bytes / (ms_per * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
              "roofline_ms": round(roof_ms, 4), "frac_of_roofline_time": round(roof_ms / ms_per, 4),
              "note": "algorithmic bytes of the whole product over its measured time; roofline_ms sums each "
-                     "kernel family at its own bound (HBM, or the FP64 vector peak for near blocks held in "
-                     "the caches)"}
+                     "kernel family at its own bound (HBM, or the FP64 peak for near blocks held in the "
+                     "caches)"}
     near_avg_launch_ms = near_ms / max(near_launches, 1)
     if coup_ms >= near_ms:
         roofline = {"bound": "hbm", "kernel": coup_kernel, "achieved": round(coup_bytes / (coup_ms * 1e-3) / 1e9, 2),
