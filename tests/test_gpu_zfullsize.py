@@ -52,10 +52,19 @@ def test_cube64_product_matches_oracle(full, capsys):
     rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
     assert rel <= 1e-12
     assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+    # the product above runs the tiled near field (stored-once 64 x 64 blocks on the
+    # matrix cores); the per-leaf kernel in passes must agree as well
+    assert H.near_tiles() == (True, True)
+    H.near_tiles(False)
+    yl = H.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    H.near_tiles(True)
+    rel_l = np.linalg.norm(yl - yo) / np.linalg.norm(yo)
+    assert rel_l <= 1e-12 and np.linalg.norm(y - yl) <= 1e-13 * np.linalg.norm(yl)
     y32 = H.matvec(torch.from_numpy(x.astype(np.complex64)).cuda(), precision="fp32").cpu().numpy()
     e32 = np.linalg.norm(y32 - yo) / np.linalg.norm(yo)
     with capsys.disabled():
-        print(f"[fullsize] fp64 rel err {rel:.2e}, fp32 tier rel err {e32:.2e}", flush=True)
+        print(f"[fullsize] fp64 rel err {rel:.2e} (per-leaf near kernel {rel_l:.2e}), fp32 tier rel err {e32:.2e}",
+              flush=True)
     assert e32 <= 1e-5
 
 
