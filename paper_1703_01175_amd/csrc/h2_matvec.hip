@@ -774,7 +774,7 @@ __global__ __launch_bounds__(512) void k_near_tile(
 // operand runs two k steps ahead across steps.  Group h leaves its sums in part[h]
 // (tree order); k_near_tile_finish adds the two and finishes the rows.
 template <bool M3>
-__global__ __launch_bounds__(256) void k_near_tile_split(
+__global__ __launch_bounds__(256, 2) void k_near_tile_split(
     const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf, const int64_t* __restrict__ step_off,
     const int* __restrict__ step_src, const double2* __restrict__ near, const double2* __restrict__ zsrc,
     const int* __restrict__ cl_begin, const int* __restrict__ cl_size, const double2* __restrict__ U,
