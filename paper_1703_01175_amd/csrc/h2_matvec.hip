@@ -34,6 +34,14 @@ __device__ __forceinline__ void cfma(TV& acc, TB a, TV b) {
 
 template <typename TV> __device__ __forceinline__ TV czero() { TV z; z.x = 0; z.y = 0; return z; }
 
+// FP64 matrix-core product D = A B + C on 16 x 16 x 4 tiles (one double of A and of B
+// per lane, four of D).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Streaming (nontemporal) loads of block data: read once per product, kept out
 // of the caches that hold the reused vectors.
 __device__ __forceinline__ double2 ldnt(const double2* p) {
@@ -436,13 +444,116 @@ __device__ __forceinline__ void coupling_sym_row(int kt, int nown, const TB* __r
     }
 }
 
+// FP64 rows of rank up to 16: the transposed products on the matrix cores, the
+// forward product on the vector units, from the same loads.  A 16-column group of the
+// owned columns is one 16 x 16 tile: lane l holds column 16 g + l % 16, rows
+// 4 s + l / 16 (s < 4) of the block.  Those four values are the A operands of the
+// four 16 x 16 x 4 steps of S^T X_t (A[m][k]: column m, row k of the step; B: rows of
+// X_t x component, 3 of 16 used; complex in the 3M form), and they also take the lane's
+// forward terms S[i][j] X_s[j] for its four rows, summed over the lane's columns and,
+// once per row cluster, over the 16 lanes of each DPP row.  Each wave takes every fourth
+// group; two groups' loads are in flight.
+__device__ __forceinline__ void coupling_sym_mfma16(int kt, int nown, const double2* __restrict__ S,
+                                                    const int* __restrict__ src, const double2* __restrict__ Xh,
+                                                    double2* __restrict__ yt, const double2* __restrict__ xt_src,
+                                                    double2* __restrict__ part, const double2* __restrict__ zero,
+                                                    double2 (*red)[3]) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int rl = lane & 15, kq = lane >> 4;
+    const int ng = (nown + 15) >> 4;
+    // B operands of the transposed steps: X_t row 4 s + l / 16, component l % 16
+    double2 bt[4];
+    double bs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + kq;
+        bt[q] = *(i < kt && rl < kNcomp ? xt_src + i * kNcomp + rl : zero);
+        bs[q] = bt[q].x + bt[q].y;
+    }
+    double2 fa[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fa[q][c] = czero<double2>();
+    struct Grp {
+        double2 s[4];
+        double2 x[3];
+    };
+    auto load = [&](int g) {
+        const int j = 16 * g + rl;
+        const bool ok = j < nown;
+        Grp o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * q + kq;
+            o.s[q] = *(ok && i < kt ? S + (int64_t)j * kt + i : zero);
+        }
+        const double2* xs = ok ? Xh + (int64_t)src[j] * kNcomp : zero;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o.x[c] = xs[c];
+        return o;
+    };
+    auto work = [&](const Grp& o, int g) {
+        // forward terms of the lane's four rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) cfma(fa[q][c], o.s[q], o.x[c]);
+        // transposed: D[column][component] over the 16 rows, 3M form
+        v4d p1 = {0, 0, 0, 0}, p2 = p1, p3 = p1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            p1 = mfma64(o.s[q].x, bt[q].x, p1);
+            p2 = mfma64(o.s[q].y, bt[q].y, p2);
+            p3 = mfma64(o.s[q].x + o.s[q].y, bs[q], p3);
+        }
+        // register r of lane l: column 16 g + 4 r + l / 16, component l % 16
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 16 * g + 4 * r + kq;
+            if (j < nown && rl < kNcomp)
+                part[(int64_t)j * kNcomp + rl] = make_double2(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
+        }
+    };
+    const int mine = ng > w ? (ng - 1 - w) / 4 + 1 : 0;
+    if (mine > 0) {
+        Grp a = load(w), b = load(w + 4);
+        for (int i = 0; i < mine; i += 2) {
+            const int g = w + 4 * i;
+            work(a, g);
+            a = load(g + 8);
+            __builtin_amdgcn_sched_barrier(0);
+            work(b, g + 4);              // past this wave's last group: zeros, nothing stored
+            b = load(g + 12);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // forward rows: sum over the 16 lanes of each DPP row, then over the 4 waves
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fa[q][c] = col_sum<16>(fa[q][c]);
+    if (rl == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red[w * 16 + 4 * q + kq][c] = fa[q][c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kt * kNcomp; e += 256) {
+        const int r = e / kNcomp, c = e % kNcomp;
+        yt[e] = cadd(cadd(red[r][c], red[16 + r][c]), cadd(red[32 + r][c], red[48 + r][c]));
+    }
+}
+
 template <typename TB, typename TV>
 __global__ __launch_bounds__(256) void k_coupling_sym(const int* __restrict__ row_cl, const int64_t* __restrict__ row_off,
                                                       const int* __restrict__ row_colptr, const int* __restrict__ colsrc,
                                                       const int* __restrict__ row_nown, const int* __restrict__ row_pbase,
                                                       const int* __restrict__ cl_rank, const int* __restrict__ cl_coef,
                                                       const TB* __restrict__ coupling, const TV* __restrict__ Xh,
-                                                      TV* __restrict__ Yh, TV* __restrict__ part) {
+                                                      TV* __restrict__ Yh, TV* __restrict__ part,
+                                                      const double2* __restrict__ zero) {
     __shared__ TV red[256][3];
     const int slot = blockIdx.x;
     const int t = row_cl[slot];
@@ -454,6 +565,12 @@ __global__ __launch_bounds__(256) void k_coupling_sym(const int* __restrict__ ro
     TV* pt = part + (int64_t)row_pbase[slot] * kNcomp;
     const TV* xt = Xh + (int64_t)co * kNcomp;
     TV* yt = Yh + (int64_t)co * kNcomp;
+    if constexpr (std::is_same<TV, double2>::value && std::is_same<TB, double2>::value) {
+        if (kt <= 16) {
+            coupling_sym_mfma16(kt, nown, S, src, Xh, yt, xt, pt, zero, red);
+            return;
+        }
+    }
     if (kt <= 16)
         coupling_sym_row<TB, TV, 4>(kt, nown, S, src, Xh, yt, xt, pt, red);
     else if (kt <= 32)
@@ -625,14 +742,9 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 // target's rows are finished as in k_near_epilogue.
 // part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
 // 2: both in one launch.
-typedef double v4d __attribute__((ext_vector_type(4)));
 // complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur + Ui))
 // instead of four
 constexpr bool kTile3M = true;
-
-__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // One k step's operands: 4 columns of G (16 rows a wave) and the matching 4 rows of
 // the 16 sources, for the three field components.
@@ -1177,7 +1289,8 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
             if (d.coup_sym) {
                 k_coupling_sym<TB, TV><<<d.n_rowcl, 256, 0, s>>>(d.row_cl, d.row_off, d.row_colptr, d.colsrc,
                                                                  d.row_nown, d.row_pbase, d.cl_rank, d.cl_coef,
-                                                                 coupling, Xh, Yh, (TV*)d.cpart);
+                                                                 coupling, Xh, Yh, (TV*)d.cpart,
+                                                                 (const double2*)d.zero_block);
                 end(3);
                 begin(7);
                 k_coupling_recv<TV><<<d.n_rowcl, 64, 0, s>>>(d.row_cl, d.crecv_ptr, d.crecv_p, d.cl_rank, d.cl_coef,
