@@ -394,9 +394,10 @@ h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* availab
  * S_ts X_s to its coefficients and writes S_ts^T X_t for the other, which adds
  * those partials before the backward transformation.  This halves the coupling
  * stream; results agree with the full mode to rounding.  Handles start in the
- * full mode: on MI355X the symmetric kernel, whose transposed products need a
- * butterfly sum per column, takes as long for half the bytes as the full kernel
- * for all of them.
+ * full mode: on MI355X the symmetric kernel (transposed products of FP64 rows of
+ * rank up to 16 on the matrix cores, a butterfly sum per column otherwise) and the
+ * pass that adds the partials take about as long for half the bytes as the full
+ * kernel for all of them.
  *   set: -1 query only, 0 every ordered block, 1 the symmetric mode
  *   *mode, *available: as for h2_near_mode (either may be NULL).
  * The multi-RHS products and the BF16x3 tier stream every block.
