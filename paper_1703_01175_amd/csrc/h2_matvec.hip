@@ -480,7 +480,13 @@ __device__ __forceinline__ void coupling_sym_mfma16(int kt, int nown, const doub
         double2 s[4];
         double2 x[3];
     };
-    auto load = [&](int g) {
+    // the lane's gather index in group g (0 past the end), requested two groups before
+    // the group's loads: a load whose address waits for it waits for every older request
+    auto gidx = [&](int g) {
+        const int j = 16 * g + rl;
+        return src[j < nown ? j : 0];
+    };
+    auto load = [&](int g, int sj) {
         const int j = 16 * g + rl;
         const bool ok = j < nown;
         Grp o;
@@ -489,7 +495,7 @@ __device__ __forceinline__ void coupling_sym_mfma16(int kt, int nown, const doub
             const int i = 4 * q + kq;
             o.s[q] = *(ok && i < kt ? S + (int64_t)j * kt + i : zero);
         }
-        const double2* xs = ok ? Xh + (int64_t)src[j] * kNcomp : zero;
+        const double2* xs = ok ? Xh + (int64_t)sj * kNcomp : zero;
 #pragma unroll
         for (int c = 0; c < 3; ++c) o.x[c] = xs[c];
         return o;
@@ -518,14 +524,19 @@ __device__ __forceinline__ void coupling_sym_mfma16(int kt, int nown, const doub
     };
     const int mine = ng > w ? (ng - 1 - w) / 4 + 1 : 0;
     if (mine > 0) {
-        Grp a = load(w), b = load(w + 4);
+        int ga = gidx(w), gb = gidx(w + 4);
+        Grp a = load(w, ga), b = load(w + 4, gb);
+        ga = gidx(w + 8);
+        gb = gidx(w + 12);
         for (int i = 0; i < mine; i += 2) {
             const int g = w + 4 * i;
             work(a, g);
-            a = load(g + 8);
+            a = load(g + 8, ga);
+            ga = gidx(g + 16);
             __builtin_amdgcn_sched_barrier(0);
             work(b, g + 4);              // past this wave's last group: zeros, nothing stored
-            b = load(g + 12);
+            b = load(g + 12, gb);
+            gb = gidx(g + 20);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
