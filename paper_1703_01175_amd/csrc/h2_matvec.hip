@@ -120,6 +120,8 @@ __global__ __launch_bounds__(64) void k_leaf_forward(const int* __restrict__ lea
     for (int a = threadIdx.x; a < k; a += 64) {
         TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
         const TB* col = V + (int64_t)a * n;
+        // unrolled so that several loads are in flight (the loop is latency-bound)
+#pragma unroll 8
         for (int i = 0; i < n; ++i) {
             TB v = col[i];
             cfma(acc0, v, su[i * 3 + 0]);
@@ -148,6 +150,7 @@ __global__ __launch_bounds__(64) void k_transfer_up(const int* __restrict__ list
             if (kc == 0) continue;
             const TB* T = transfer + cl_toff[ch] + (int64_t)a * kc;
             const TV* xc = Xh + (int64_t)cl_coef[ch] * kNcomp;
+#pragma unroll 8
             for (int b = 0; b < kc; ++b) {
                 TB tv = T[b];
                 cfma(acc0, tv, xc[b * 3 + 0]);
@@ -624,6 +627,7 @@ __global__ __launch_bounds__(64) void k_transfer_down(const int* __restrict__ li
     const TV* yp = Yh + (int64_t)cl_coef[p] * kNcomp;
     for (int b = threadIdx.x; b < kc; b += 64) {
         TV acc0 = czero<TV>(), acc1 = czero<TV>(), acc2 = czero<TV>();
+#pragma unroll 8
         for (int a = 0; a < kp; ++a) {
             TB tv = T[(int64_t)a * kc + b];
             cfma(acc0, tv, yp[a * 3 + 0]);
