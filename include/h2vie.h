@@ -405,20 +405,21 @@ h2_status h2_near_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* availab
  * mode is not available. */
 h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* available);
 
-/* Tiled near field of the FP64 single-vector product in the full near mode,
- * available when identical near blocks are stored once (the default on uniform
- * voxel grids; Sec. IV.B's near-field block products, unchanged).  Leaves
+/* Tiled near field of the single-vector FP64 and FP32 products in the full near
+ * mode, available when identical near blocks are stored once (the default on
+ * uniform voxel grids; Sec. IV.B's near-field block products, unchanged).  Leaves
  * consecutive in tree order form tiles of 16; a tile applies each stored block
- * that its leaves use to all of their sources at once, on the FP64 matrix cores
- * (16 x 16 x 4 products; the block is read once per tile instead of once per
- * leaf pair; each complex product as three real ones, Gr Ur, Gi Ui and
- * (Gr + Gi)(Ur + Ui)).  Results agree with the per-leaf kernel to rounding (the
- * products are formed and summed in another order).
+ * that its leaves use to all of their sources at once, on the matrix cores
+ * (16 x 16 x 4 products in the tier's precision; the block is read once per tile
+ * instead of once per leaf pair).  FP64 forms each complex product as three real
+ * ones, Gr Ur, Gi Ui and (Gr + Gi)(Ur + Ui); FP32 as four.  Results agree with
+ * the per-leaf kernel to rounding (the products are formed and summed in another
+ * order).
  *   set: -1 query only, 0 the per-leaf kernel, 1 the tiled kernel
- *   *on: 1 if FP64 full-mode products use the tiles after the call;
+ *   *on: 1 if full-mode FP64 and FP32 products use the tiles after the call;
  *   *available: 1 if the handle has tiles (either output may be NULL).
- * Handles with tiles start with them on.  The symmetric near mode, the FP32 and
- * BF16x3 tiers and the multi-RHS products do not use them.
+ * Handles with tiles start with them on.  The symmetric near mode, the BF16x3
+ * tier and the multi-RHS products do not use them.
  * Errors: BAD_HANDLE; INVALID_ARG for set outside {-1, 0, 1} or set = 1 without
  * tiles. */
 h2_status h2_near_tiles(h2_handle h, int32_t set, int32_t* on, int32_t* available);

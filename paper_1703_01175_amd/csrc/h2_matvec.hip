@@ -757,26 +757,57 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 // target's rows are finished as in k_near_epilogue.
 // part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
 // 2: both in one launch.
-// complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur + Ui))
-// instead of four
-constexpr bool kTile3M = true;
+// FP64 complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur +
+// Ui)) instead of four.  FP32 keeps the four: its matrix cores run at twice the FP64
+// rate, and the 3M imaginary part loses the digits that Gr Ur and Gi Ui cancel, which
+// FP32 cannot spare.
+template <typename TV> constexpr bool kTile3M = std::is_same<TV, double2>::value;
+
+// Precision of the tiled products: FP64 (v_mfma_f64_16x16x4f64) or FP32
+// (v_mfma_f32_16x16x4f32), same operand layouts (lane l: A[l % 16][l / 16],
+// B[l / 16][l % 16]); result register r of lane l is row drow(r, l / 16), column
+// l % 16, with drow = 4 r + l / 16 in FP64 and 4 (l / 16) + r in FP32 (both checked on
+// the device).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename TV> struct Tile;
+template <> struct Tile<double2> {
+    using R = double;
+    using V4 = v4d;
+    __device__ static V4 mma(double a, double b, V4 c) { return mfma64(a, b, c); }
+    __device__ static int drow(int r, int kq) { return 4 * r + kq; }
+};
+template <> struct Tile<float2> {
+    using R = float;
+    using V4 = v4f;
+    __device__ static V4 mma(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int r, int kq) { return 4 * kq + r; }
+};
+
+template <typename TV> __device__ __forceinline__ TV cmake(typename Real<TV>::T x, typename Real<TV>::T y) {
+    TV v;
+    v.x = x;
+    v.y = y;
+    return v;
+}
 
 // One k step's operands: 4 columns of G (16 rows a wave) and the matching 4 rows of
 // the 16 sources, for the three field components.
-struct TileOps {
-    double2 a, u0, u1, u2;
+template <typename TV> struct TileOps {
+    TV a, u0, u1, u2;
 };
 
-__device__ __forceinline__ TileOps tile_load(const double2* __restrict__ gp, const double2* __restrict__ up,
-                                            const double2* __restrict__ zero, int nt, int ns, int k0, int kq) {
+template <typename TV>
+__device__ __forceinline__ TileOps<TV> tile_load(const TV* __restrict__ gp, const TV* __restrict__ up,
+                                                const TV* __restrict__ zero, int nt, int ns, int k0, int kq) {
     // columns past n_s take their G entry from the zero block (the address is chosen
     // before the load, so nothing waits for the loaded value until its use) and read
     // row 0 of the source
     const int k = k0 + kq;
     const bool ok = k < ns;
-    TileOps o;
+    TileOps<TV> o;
     o.a = *(ok ? gp + (int64_t)k * nt : zero);
-    const double2* u = up + (ok ? k : 0) * kNcomp;
+    const TV* u = up + (ok ? k : 0) * kNcomp;
     o.u0 = u[0];
     o.u1 = u[1];
     o.u2 = u[2];
@@ -786,52 +817,80 @@ __device__ __forceinline__ TileOps tile_load(const double2* __restrict__ gp, con
 // acc[c][q], component c: with four real products q = 0 re, 1 im; with three (M3,
 // the 3M form) q = 0 Gr Ur, 1 Gi Ui, 2 (Gr + Gi)(Ur + Ui), so re = [0] - [1] and
 // im = [2] - [0] - [1]
-template <bool M3>
-__device__ __forceinline__ void tile_mma(const TileOps& o, v4d (&acc)[3][3]) {
-    const double2 u[3] = {o.u0, o.u1, o.u2};
+template <bool M3, typename TV>
+__device__ __forceinline__ void tile_mma(const TileOps<TV>& o, typename Tile<TV>::V4 (&acc)[3][3]) {
+    using T = Tile<TV>;
+    const TV u[3] = {o.u0, o.u1, o.u2};
     if constexpr (M3) {
-        const double sa = o.a.x + o.a.y;
+        const auto sa = o.a.x + o.a.y;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            acc[c][0] = mfma64(o.a.x, u[c].x, acc[c][0]);
-            acc[c][1] = mfma64(o.a.y, u[c].y, acc[c][1]);
-            acc[c][2] = mfma64(sa, u[c].x + u[c].y, acc[c][2]);
+            acc[c][0] = T::mma(o.a.x, u[c].x, acc[c][0]);
+            acc[c][1] = T::mma(o.a.y, u[c].y, acc[c][1]);
+            acc[c][2] = T::mma(sa, u[c].x + u[c].y, acc[c][2]);
         }
     } else {
-        const double nai = -o.a.y;
+        const auto nai = -o.a.y;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            acc[c][0] = mfma64(o.a.x, u[c].x, acc[c][0]);
-            acc[c][1] = mfma64(o.a.x, u[c].y, acc[c][1]);
+            acc[c][0] = T::mma(o.a.x, u[c].x, acc[c][0]);
+            acc[c][1] = T::mma(o.a.x, u[c].y, acc[c][1]);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            acc[c][0] = mfma64(nai, u[c].y, acc[c][0]);
-            acc[c][1] = mfma64(o.a.y, u[c].x, acc[c][1]);
+            acc[c][0] = T::mma(nai, u[c].y, acc[c][0]);
+            acc[c][1] = T::mma(o.a.y, u[c].x, acc[c][1]);
         }
     }
 }
 
-template <bool M3>
+// FP32 sums each step's products (one stored block times its sources) in accumulators
+// of their own and adds them to running totals at the step's end: a block product,
+// then a sum over blocks, as the tier's error bound assumes.  FP64 chains every step
+// in the same accumulators (tot is unused).
+template <bool M3, typename TV>
+__device__ __forceinline__ void tile_flush(typename Tile<TV>::V4 (&acc)[3][3], typename Tile<TV>::V4 (&tot)[3][3]) {
+    if constexpr (!std::is_same<TV, double2>::value) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < (M3 ? 3 : 2); ++q) {
+                tot[c][q] += acc[c][q];
+                acc[c][q] = typename Tile<TV>::V4{0, 0, 0, 0};
+            }
+    }
+}
+// the sums of all steps back in acc
+template <bool M3, typename TV>
+__device__ __forceinline__ void tile_total(typename Tile<TV>::V4 (&acc)[3][3], typename Tile<TV>::V4 (&tot)[3][3]) {
+    if constexpr (!std::is_same<TV, double2>::value) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < (M3 ? 3 : 2); ++q) acc[c][q] = tot[c][q];
+    }
+}
+
+template <typename TV, bool M3>
 __global__ __launch_bounds__(512) void k_near_tile(
     int part, const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf,
     const int64_t* __restrict__ step_off, const int* __restrict__ step_shape, const int* __restrict__ step_src,
-    const double2* __restrict__ near, const double2* __restrict__ zsrc, double2* __restrict__ ypart,
+    const TV* __restrict__ near, const TV* __restrict__ zsrc, TV* __restrict__ ypart,
     const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
-    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const double2* __restrict__ basis,
-    const double2* __restrict__ U, const double2* __restrict__ Yh, const int* __restrict__ perm,
-    const double2* __restrict__ x, double2* __restrict__ y, int op, double alpha) {
-    __shared__ double2 red[kMaxLeaf][kTileLeaves][kNcomp];
+    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const TV* __restrict__ basis,
+    const TV* __restrict__ U, const TV* __restrict__ Yh, const int* __restrict__ perm,
+    const TV* __restrict__ x, TV* __restrict__ y, int op, typename Real<TV>::T alpha) {
+    __shared__ TV red[kMaxLeaf][kTileLeaves][kNcomp];
     const int tile = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rl = lane & 15, kq = lane >> 4;
     const int row = 16 * (w & 3) + rl;
-    v4d acc[3][3];
+    typename Tile<TV>::V4 acc[3][3], tot[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[c][q] = v4d{0, 0, 0, 0};
+        for (int q = 0; q < 3; ++q) acc[c][q] = tot[c][q] = typename Tile<TV>::V4{0, 0, 0, 0};
     if (part != 1) {
         const int e = tile_ptr[tile + 1];
         for (int st = tile_ptr[tile] + (w >> 2); st < e; st += 2) {
@@ -840,45 +899,49 @@ __global__ __launch_bounds__(512) void k_near_tile(
             const int sb = step_src[(int64_t)st * kTileLeaves + rl];
             // rows past n_t only reach rows that are never finished, so they read row 0;
             // a slot without a source reads a block of zeros
-            const double2* gp = near + step_off[st] + (row < nt ? row : 0);
-            const double2* up = sb >= 0 ? U + (int64_t)sb * kNcomp : zsrc;
+            const TV* gp = near + step_off[st] + (row < nt ? row : 0);
+            const TV* up = sb >= 0 ? U + (int64_t)sb * kNcomp : zsrc;
             // two k steps in flight: each register set is reloaded right after its use,
             // so no loaded register is copied (a copy would wait for its load)
-            TileOps p = tile_load(gp, up, zsrc, nt, ns, 0, kq);
-            TileOps q = tile_load(gp, up, zsrc, nt, ns, 4, kq);
+            TileOps<TV> p = tile_load(gp, up, zsrc, nt, ns, 0, kq);
+            TileOps<TV> q = tile_load(gp, up, zsrc, nt, ns, 4, kq);
             // (the scheduling barriers keep each reload where it is written: left alone,
             // the scheduler sinks every load to just before its use)
             for (int k0 = 0; k0 < ns; k0 += 8) {
-                tile_mma<M3>(p, acc);
+                tile_mma<M3, TV>(p, acc);
                 p = tile_load(gp, up, zsrc, nt, ns, k0 + 8, kq);
                 __builtin_amdgcn_sched_barrier(0);
-                tile_mma<M3>(q, acc);
+                tile_mma<M3, TV>(q, acc);
                 q = tile_load(gp, up, zsrc, nt, ns, k0 + 12, kq);
                 __builtin_amdgcn_sched_barrier(0);
             }
+            tile_flush<M3, TV>(acc, tot);
         }
+        tile_total<M3, TV>(acc, tot);
     }
     // the two halves' sums meet in LDS: red[row][slot][component]
-    double2 v[3][4];
+    TV v[3][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            v[c][r] = M3 ? make_double2(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
-                         : make_double2(acc[c][0][r], acc[c][1][r]);
-    const int r0 = 16 * (w & 3) + kq;
+            v[c][r] = M3 ? cmake<TV>(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
+                         : cmake<TV>(acc[c][0][r], acc[c][1][r]);
+    const int r0 = 16 * (w & 3);
     if (w >= 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[r0 + 4 * r][rl][c] = v[c][r];
+            for (int c = 0; c < 3; ++c) red[r0 + Tile<TV>::drow(r, kq)][rl][c] = v[c][r];
     }
     __syncthreads();
     if (w < 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r) {
+            const int i = r0 + Tile<TV>::drow(r, kq);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[r0 + 4 * r][rl][c] = cadd(red[r0 + 4 * r][rl][c], v[c][r]);
+            for (int c = 0; c < 3; ++c) red[i][rl][c] = cadd(red[i][rl][c], v[c][r]);
+        }
     }
     __syncthreads();
     const int pass = part == 1 ? 1 : 0, npass = part == 2 ? 1 : 2;
@@ -887,7 +950,7 @@ __global__ __launch_bounds__(512) void k_near_tile(
         if (t < 0) continue;
         const int n = cl_size[t];
         if (lane < n)
-            near_finish_row<double2, double2>(t, n, lane, red[lane][j][0], red[lane][j][1], red[lane][j][2], pass,
+            near_finish_row<TV, TV>(t, n, lane, red[lane][j][0], red[lane][j][1], red[lane][j][2], pass,
                                               npass, ypart, cl_rank, cl_coef, cl_begin, cl_basis_off, basis, Yh,
                                               perm, x, y, op, alpha);
     }
@@ -900,32 +963,32 @@ __global__ __launch_bounds__(512) void k_near_tile(
 // columns of the block; the group's sources are staged in one LDS buffer; the A
 // operand runs two k steps ahead across steps.  Group h leaves its sums in part[h]
 // (tree order); k_near_tile_finish adds the two and finishes the rows.
-template <bool M3>
+template <typename TV, bool M3>
 __global__ __launch_bounds__(256, 2) void k_near_tile_split(
     const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf, const int64_t* __restrict__ step_off,
-    const int* __restrict__ step_src, const double2* __restrict__ near, const double2* __restrict__ zsrc,
-    const int* __restrict__ cl_begin, const int* __restrict__ cl_size, const double2* __restrict__ U,
-    double2* __restrict__ part0, double2* __restrict__ part1) {
+    const int* __restrict__ step_src, const TV* __restrict__ near, const TV* __restrict__ zsrc,
+    const int* __restrict__ cl_begin, const int* __restrict__ cl_size, const TV* __restrict__ U,
+    TV* __restrict__ part0, TV* __restrict__ part1) {
     constexpr int kSlice = kMaxLeaf * kNcomp;
     constexpr int kChunks = kTileLeaves * kSlice / 256;        // entries each thread stages per step
     constexpr int kSteps = kMaxLeaf / 4;                       // k steps of 4 columns
     constexpr int kRowStride = kTileLeaves * kNcomp;
-    __shared__ double2 stage[kMaxLeaf][kTileLeaves][kNcomp];
+    __shared__ TV stage[kMaxLeaf][kTileLeaves][kNcomp];
     const int tile = blockIdx.x >> 1, h = blockIdx.x & 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rl = lane & 15, kq = lane >> 4;
     const int row = 16 * w + rl;
-    v4d acc[3][3];
+    typename Tile<TV>::V4 acc[3][3], tot[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[c][q] = v4d{0, 0, 0, 0};
+        for (int q = 0; q < 3; ++q) acc[c][q] = tot[c][q] = typename Tile<TV>::V4{0, 0, 0, 0};
     const int b = tile_ptr[tile] + h, e = tile_ptr[tile + 1];
     if (b < e) {
         int sb[kChunks];
-        double2 sv[kChunks];
+        TV sv[kChunks];
         auto srcs = [&](int st) {
 #pragma unroll
             for (int j = 0; j < kChunks; ++j) sb[j] = step_src[(int64_t)st * kTileLeaves + (tid + 256 * j) / kSlice];
@@ -940,7 +1003,7 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
             for (int j = 0; j < kChunks; ++j) {
                 const int i = tid + 256 * j;
                 const int n = i / kSlice, o = i % kSlice;
-                double2 v = sv[j];
+                TV v = sv[j];
                 asm volatile("" : "+v"(v.x), "+v"(v.y));
                 stage[o / kNcomp][n][o % kNcomp] = v;
             }
@@ -952,15 +1015,15 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
         fetch();
         store();
         srcs(last(b + 2));
-        const double2* ga = aptr(b);
-        double2 a0 = ga[0], a1 = ga[4 * kMaxLeaf];
+        const TV* ga = aptr(b);
+        TV a0 = ga[0], a1 = ga[4 * kMaxLeaf];
         __syncthreads();
         for (int st = b; st < e; st += 2) {
             fetch();                                            // slices of step st + 2
             srcs(last(st + 4));
-            const double2* gn = aptr(last(st + 2));
-            const double2* bs = &stage[0][0][0] + (kq * kTileLeaves + rl) * kNcomp;
-            double2 bu[2][3];
+            const TV* gn = aptr(last(st + 2));
+            const TV* bs = &stage[0][0][0] + (kq * kTileLeaves + rl) * kNcomp;
+            TV bu[2][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) bu[0][c] = bs[c];
 #pragma unroll
@@ -969,40 +1032,42 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
 #pragma unroll
                     for (int c = 0; c < 3; ++c) bu[(i + 1) & 1][c] = bs[(i + 1) * 4 * kRowStride + c];
                 }
-                TileOps o;
+                TileOps<TV> o;
                 o.a = (i & 1) ? a1 : a0;
                 o.u0 = bu[i & 1][0];
                 o.u1 = bu[i & 1][1];
                 o.u2 = bu[i & 1][2];
-                tile_mma<M3>(o, acc);
-                const double2* src = i + 2 < kSteps ? ga + (i + 2) * 4 * kMaxLeaf : gn + (i + 2 - kSteps) * 4 * kMaxLeaf;
+                tile_mma<M3, TV>(o, acc);
+                const TV* src = i + 2 < kSteps ? ga + (i + 2) * 4 * kMaxLeaf : gn + (i + 2 - kSteps) * 4 * kMaxLeaf;
                 if (i & 1)
                     a1 = *src;
                 else
                     a0 = *src;
                 __builtin_amdgcn_sched_barrier(0);
             }
+            tile_flush<M3, TV>(acc, tot);
             ga = gn;
             __syncthreads();                                    // every wave is done with the buffer
             store();
             __syncthreads();
         }
+        tile_total<M3, TV>(acc, tot);
     }
-    // sums to this group's partial buffer: register r of lane l is row 4 r + l / 16 of
+    // sums to this group's partial buffer: register r of lane l is row drow(r, l / 16) of
     // the wave's 16, slot l % 16
-    double2* out = h ? part1 : part0;
+    TV* out = h ? part1 : part0;
     const int t = tile_leaf[tile * kTileLeaves + rl];
     if (t >= 0) {
         const int n = cl_size[t];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = 16 * w + 4 * r + kq;
+            const int i = 16 * w + Tile<TV>::drow(r, kq);
             if (i < n) {
-                double2* o = out + (int64_t)(cl_begin[t] + i) * kNcomp;
+                TV* o = out + (int64_t)(cl_begin[t] + i) * kNcomp;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    o[c] = M3 ? make_double2(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
-                              : make_double2(acc[c][0][r], acc[c][1][r]);
+                    o[c] = M3 ? cmake<TV>(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
+                              : cmake<TV>(acc[c][0][r], acc[c][1][r]);
             }
         }
     }
@@ -1010,18 +1075,19 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
 
 // The rows of leaf slot blockIdx.x: the two split groups' sums, the leaf backward
 // transformation and the epilogue (as k_near_epilogue's last pass).
+template <typename TV>
 __global__ __launch_bounds__(64) void k_near_tile_finish(
-    const int* __restrict__ leaf_id, const double2* __restrict__ part0, const double2* __restrict__ part1,
+    const int* __restrict__ leaf_id, const TV* __restrict__ part0, const TV* __restrict__ part1,
     const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
-    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const double2* __restrict__ basis,
-    const double2* __restrict__ Yh, const int* __restrict__ perm, const double2* __restrict__ x,
-    double2* __restrict__ y, int op, double alpha) {
+    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const TV* __restrict__ basis,
+    const TV* __restrict__ Yh, const int* __restrict__ perm, const TV* __restrict__ x,
+    TV* __restrict__ y, int op, typename Real<TV>::T alpha) {
     const int t = leaf_id[blockIdx.x];
     const int n = cl_size[t];
     const int lane = threadIdx.x;
     if (lane >= n) return;
     const int64_t i = (int64_t)(cl_begin[t] + lane) * kNcomp;
-    near_finish_row<double2, double2>(t, n, lane, cadd(part0[i], part1[i]), cadd(part0[i + 1], part1[i + 1]),
+    near_finish_row<TV, TV>(t, n, lane, cadd(part0[i], part1[i]), cadd(part0[i + 1], part1[i + 1]),
                                       cadd(part0[i + 2], part1[i + 2]), 0, 1, nullptr, cl_rank, cl_coef, cl_begin,
                                       cl_basis_off, basis, Yh, perm, x, y, op, alpha);
 }
@@ -1240,25 +1306,25 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     // full mode over stored-once blocks: all passes but the last read only U, so they
     // run on the side stream beside the upward pass, couplings and downward pass (when
     // the kernel families are timed, those passes are timed on the side stream)
-    constexpr bool fp64 = std::is_same<TV, double2>::value && std::is_same<TB, double2>::value;
-    const bool tiles = fp64 && d.near_tiles && !d.near_sym;
+    constexpr bool same = std::is_same<TV, TB>::value;     // FP64 or FP32 throughout
+    const bool tiles = same && d.near_tiles && !d.near_sym;
     const bool overlap = !d.near_sym && d.near_side && (tiles || d.near_passes > 1);
     auto near_tile = [&](int part, const TV* xr, TV* yr, hipStream_t st) {
-        if constexpr (fp64) {
+        if constexpr (same) {
             if (d.tiles_full) {
                 if (part != 1)
-                    k_near_tile_split<kTile3M><<<2 * d.n_tiles, 256, 0, st>>>(
-                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const double2*)d.zero_block, d.cl_begin,
-                        d.cl_size, U, (double2*)d.near_ypart, (double2*)d.tile_part1);
+                    k_near_tile_split<TV, kTile3M<TV>><<<2 * d.n_tiles, 256, 0, st>>>(
+                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const TV*)d.zero_block, d.cl_begin,
+                        d.cl_size, U, (TV*)d.near_ypart, (TV*)d.tile_part1);
                 if (part != 0)
-                    k_near_tile_finish<<<d.n_leaves, 64, 0, st>>>(
-                        d.leaf_id, (const double2*)d.near_ypart, (const double2*)d.tile_part1, d.cl_rank, d.cl_coef,
+                    k_near_tile_finish<TV><<<d.n_leaves, 64, 0, st>>>(
+                        d.leaf_id, (const TV*)d.near_ypart, (const TV*)d.tile_part1, d.cl_rank, d.cl_coef,
                         d.cl_begin, d.cl_size, d.cl_basis_off, basis, Yh, d.perm, xr, yr, op, alpha);
             } else {
-                k_near_tile<kTile3M><<<d.n_tiles, 512, 0, st>>>(
-                    part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near,
-                    (const double2*)d.zero_block, (double2*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size,
-                    d.cl_basis_off, basis, U, Yh, d.perm, xr, yr, op, alpha);
+                k_near_tile<TV, kTile3M<TV>><<<d.n_tiles, 512, 0, st>>>(
+                    part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near, (const TV*)d.zero_block,
+                    (TV*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh,
+                    d.perm, xr, yr, op, alpha);
             }
         }
     };

@@ -246,12 +246,12 @@ def test_overlapped_near_passes_over_several_rhs(torch):
 
 @pytest.mark.parametrize("name", CASES)
 def test_tiled_near_field_matches_per_leaf_kernel_and_oracle(torch, name):
-    """Near blocks stored once: the FP64 full-mode product applies each stored block
-    to the sources of 16 target leaves at once on the matrix cores (tiles of 16 leaves
-    consecutive in tree order).  It covers leaves of 27 voxels (cube12: columns past a
+    """Near blocks stored once: the full-mode product applies each stored block to the
+    sources of 16 target leaves at once on the matrix cores (tiles of 16 leaves
+    consecutive in tree order; FP64 and FP32 tiers).  It covers leaves of 27 voxels (cube12: columns past a
     block's width, rows past its height), tiles with empty slots (cube8: 8 leaves) and
-    every geometry here; the products match the per-leaf kernel to rounding and the
-    oracle, for Z and G.  Without stored-once blocks there are no tiles."""
+    every geometry here; FP64 products match the per-leaf kernel to rounding and the
+    oracle, for Z and G, and FP32 ones stay within the tier's bound.  Without stored-once blocks there are no tiles."""
     from paper_1703_01175_amd._lib import H2Error
     print(f"[gpu] tiled near field {name}", flush=True)
     g, d, H = operator(name)
@@ -279,6 +279,18 @@ def test_tiled_near_field_matches_per_leaf_kernel_and_oracle(torch, name):
         assert _rel(yt, yl) <= 1e-13, op
         assert _rel(yt, yo) <= 1e-12, op
         assert np.abs(yt - yo).max() <= 1e-12 * np.abs(yo).max(), op
+    # the FP32 tier: tiles on the FP32 matrix cores, within the tier's bound
+    x32 = torch.from_numpy(x.astype(np.complex64)).cuda()
+    yt32 = H.matvec(x32, precision="fp32").cpu().numpy()
+    H.near_tiles(False)
+    yl32 = H.matvec(x32, precision="fp32").cpu().numpy()
+    H.near_tiles(True)
+    yo = om.h2_matvec(d, x)
+    e_emu = _rel(oprec.h2_matvec_tier(d, x, "fp32"), yo)
+    e_t, e_l = _rel(yt32, yo), _rel(yl32, yo)
+    print(f"[gpu] fp32 {name}: tiles {e_t:.2e} per-leaf {e_l:.2e} emulated {e_emu:.2e}", flush=True)
+    assert e_t <= 1e-5 and e_t <= 2.0 * e_emu
+    assert _rel(yt32, yl32) <= 2.0 * e_emu
     H.near_mode(sym0)
 
 
