@@ -247,6 +247,7 @@ def main():
         extra["near_per_leaf_kernel"]["max_rel_diff_vs_headline"] = float(
             np.linalg.norm(y.cpu().numpy() - result_gpu) / np.linalg.norm(result_gpu))
         H.near_tiles(True)
+    extra["fp32_tier_product"] = fp32_product_leg(H, x, result_gpu, args.steps, args.warmup)
     if not args.no_solve:
         extra.update(solve_legs(H, b_np, dev))
     if not args.keep_all_near and not args.no_streamed:
@@ -321,6 +322,31 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def fp32_product_leg(H, x, y64, steps, warmup):
+    """Time `steps` FP32-tier products on the same handle (blocks, vectors and sums in
+    float32; the tiled near field on the FP32 matrix cores when the handle has tiles) and
+    report its error against the FP64 product."""
+    import numpy as np
+    import torch
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(warmup):
+        H.matvec(x32, precision="fp32", out=y32)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        H.matvec(x32, precision="fp32", out=y32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    y = y32.cpu().numpy().astype(np.complex128)
+    return {"ms_per_step": round(ms, 4), "matvec_per_s": round(1000.0 / ms, 3),
+            "near_tiles": bool(H.near_tiles()[0]),
+            "rel_err_vs_fp64_product": float(np.linalg.norm(y - y64) / np.linalg.norm(y64))}
 
 
 def product_leg(H, d, x, y, steps, warmup, workload):
