@@ -411,10 +411,9 @@ h2_status h2_coupling_mode(h2_handle h, int32_t set, int32_t* mode, int32_t* ava
  * consecutive in tree order form tiles of 16; a tile applies each stored block
  * that its leaves use to all of their sources at once, on the matrix cores
  * (16 x 16 x 4 products in the tier's precision; the block is read once per tile
- * instead of once per leaf pair).  FP64 forms each complex product as three real
- * ones, Gr Ur, Gi Ui and (Gr + Gi)(Ur + Ui); FP32 as four.  Results agree with
- * the per-leaf kernel to rounding (the products are formed and summed in another
- * order).
+ * instead of once per leaf pair), each complex product as three real ones, Gr Ur,
+ * Gi Ui and (Gr + Gi)(Ur + Ui).  Results agree with the per-leaf kernel to
+ * rounding (the products are formed and summed in another order).
  *   set: -1 query only, 0 the per-leaf kernel, 1 the tiled kernel
  *   *on: 1 if full-mode FP64 and FP32 products use the tiles after the call;
  *   *available: 1 if the handle has tiles (either output may be NULL).

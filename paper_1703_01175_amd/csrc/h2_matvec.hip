@@ -757,11 +757,9 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 // target's rows are finished as in k_near_epilogue.
 // part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
 // 2: both in one launch.
-// FP64 complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur +
-// Ui)) instead of four.  FP32 keeps the four: its matrix cores run at twice the FP64
-// rate, and the 3M imaginary part loses the digits that Gr Ur and Gi Ui cancel, which
-// FP32 cannot spare.
-template <typename TV> constexpr bool kTile3M = std::is_same<TV, double2>::value;
+// complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur + Ui))
+// instead of four
+constexpr bool kTile3M = true;
 
 // Precision of the tiled products: FP64 (v_mfma_f64_16x16x4f64) or FP32
 // (v_mfma_f32_16x16x4f32), same operand layouts (lane l: A[l % 16][l / 16],
@@ -1313,7 +1311,7 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
         if constexpr (same) {
             if (d.tiles_full) {
                 if (part != 1)
-                    k_near_tile_split<TV, kTile3M<TV>><<<2 * d.n_tiles, 256, 0, st>>>(
+                    k_near_tile_split<TV, kTile3M><<<2 * d.n_tiles, 256, 0, st>>>(
                         d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const TV*)d.zero_block, d.cl_begin,
                         d.cl_size, U, (TV*)d.near_ypart, (TV*)d.tile_part1);
                 if (part != 0)
@@ -1321,7 +1319,7 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
                         d.leaf_id, (const TV*)d.near_ypart, (const TV*)d.tile_part1, d.cl_rank, d.cl_coef,
                         d.cl_begin, d.cl_size, d.cl_basis_off, basis, Yh, d.perm, xr, yr, op, alpha);
             } else {
-                k_near_tile<TV, kTile3M<TV>><<<d.n_tiles, 512, 0, st>>>(
+                k_near_tile<TV, kTile3M><<<d.n_tiles, 512, 0, st>>>(
                     part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near, (const TV*)d.zero_block,
                     (TV*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh,
                     d.perm, xr, yr, op, alpha);
