@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--max-matvec", type=int, default=6000, help="product cap of each evaluation solve for --learned")
     ap.add_argument("--pairs", type=int, default=20000, help="training (leaf, iterate) pairs for --learned")
     ap.add_argument("--epochs", type=int, default=40, help="training epochs for --learned")
+    ap.add_argument("--paper-workloads", action="store_true",
+                    help="only time the voxel versions of the paper's Sec. V.B-D workloads (rod, slab, array of "
+                         "cubes) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -186,6 +189,8 @@ def main():
     from h2gen.construct import build_h2
     from h2gen.desc import H2Desc
 
+    if args.paper_workloads:
+        return paper_workloads(args)
     if args.batched:
         return batched(args)
     if args.learned:
@@ -494,6 +499,70 @@ def product_leg(H, d, x, y, steps, warmup, workload):
                          "elems": int(st["near_elems"])},
         "kernel_ms": fam,
     }
+
+
+PAPER_WORKLOADS = {   # Sec. V.B-D, eps_r = 2.54
+    "rod 256 wavelengths (Sec. V.B)": lambda h2gen: h2gen.paper_rod(256),
+    "slab 8 x 8 wavelengths (Sec. V.C)": lambda h2gen: h2gen.paper_slab(8),
+    # 8 voxels per 0.3-wavelength cube (h = lambda/26.7): the 56^3 bounding box splits into
+    # leaves of 27-64 voxels (at 6 voxels per cube, 42^3 gives leaves of 8-27)
+    "4^3 array of cubes (Sec. V.D)": lambda h2gen: h2gen.paper_cube_array(4, cube_voxels=8, h=0.3 / 8),
+}
+
+
+def paper_workloads(args):
+    """Voxel versions of the paper's scaling workloads, incidence along -y polarised along
+    z: host construction (eps 1e-3), FP64 products timed with HIP events, BiCGStab at the
+    paper's 1e-3 and GMRES(50) at 1e-6.  Every representation is built before the GPU is
+    touched."""
+    import h2gen
+    from h2gen.construct import build_h2
+    built = []
+    for name, make in PAPER_WORKLOADS.items():
+        g = make(h2gen)
+        t0 = time.time()
+        d = build_h2(g, eps=1e-3)
+        built.append((name, g, d, time.time() - t0))
+        log(f"[bench] {name}: {g.shape}, N = {3 * g.n_vox}, built in {built[-1][3]:.1f}s")
+    import torch
+    from paper_1703_01175_amd import H2Operator
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, g, d, build_s in built:
+        H = H2Operator(d, tiers=("fp64",), device="cuda:0")
+        x = torch.from_numpy(h2gen.random_vector(3 * g.n_vox, 1)).to(dev)
+        y = torch.empty_like(x)
+        for _ in range(args.warmup):
+            H.matvec(x, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            H.matvec(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        b = torch.from_numpy(h2gen.paper_excitation(g)).to(dev)
+        H.bicgstab(b, tol=1e-3, max_matvec=2)                # warm-up
+        H.gmres(b, tol=1e-6, restart=50, max_matvec=3)
+        rec = {"shape": list(g.shape), "N": 3 * g.n_vox, "max_rank": int(d.rank.max()),
+               "host_build_s": round(build_s, 2), "product_ms": round(ms, 4), "matvec_per_s": round(1000.0 / ms, 2)}
+        for solver, call in (("bicgstab_1e-3", lambda: H.bicgstab(b, tol=1e-3)),
+                             ("gmres50_1e-6", lambda: H.gmres(b, tol=1e-6, restart=50))):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            _, rep = call()
+            torch.cuda.synchronize()
+            rec[solver] = {"seconds": round(time.time() - t0, 4), "iterations": rep.iterations,
+                           "matvecs": rep.matvecs, "converged": rep.converged, "rel_residual": rep.rel_residual}
+        log(f"[bench] {name}: {ms:.3f} ms per product, BiCGStab 1e-3 {rec['bicgstab_1e-3']['iterations']} steps, "
+            f"GMRES 1e-6 {rec['gmres50_1e-6']['iterations']} its")
+        out[name] = rec
+        H.close()
+        del H
+        torch.cuda.empty_cache()
+    print(json.dumps({"paper_workloads": out, "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic (voxelised bodies of Sec. V.B-D, eps_r 2.54)"}), flush=True)
 
 
 def solve_legs(H, b_np, dev):

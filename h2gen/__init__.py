@@ -10,9 +10,9 @@ implemented in this package, and nothing in it is shared with either side's
 arithmetic.  Both consume the flat arrays of :class:`h2gen.desc.H2Desc`.
 """
 
-from .geometry import Geometry, cube, slab, uneven_cubes  # noqa: F401
+from .geometry import Geometry, cube, slab, uneven_cubes, paper_rod, paper_slab, paper_cube_array  # noqa: F401
 from .tree import ClusterTree, build_tree  # noqa: F401
 from .partition import Partition, build_partition  # noqa: F401
 from .desc import H2Desc  # noqa: F401
 from .construct import build_h2  # noqa: F401
-from .rhs import random_vector, plane_wave  # noqa: F401
+from .rhs import random_vector, plane_wave, plane_wave_dir, paper_excitation  # noqa: F401

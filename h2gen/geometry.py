@@ -139,3 +139,41 @@ def uneven_cubes(count=32, edge_range=(8, 48), eps_range=(1.5, 8.0), h=1.0 / 16.
         out.append(Geometry((n, n, n), h, e.astype(np.complex128), sigma=sigma,
                             name=f"ucube{i}_{n}", meta={"seed": seed, "index": i}))
     return out
+
+
+# ---------------------------------------------------------------- the paper's Sec. V bodies
+# Voxel versions of the three scaling workloads of Sec. V.B-D: relative permittivity
+# 2.54 throughout, voxel edge lambda/20 by default.  The paper discretises the bodies
+# with SWG functions; here they are voxelised on the same grid as every other body.
+
+PAPER_EPS = 2.54
+
+
+def paper_rod(length_wavelengths: float, h: float = 1.0 / 20.0) -> Geometry:
+    """Sec. V.B: a rod of cross-section lambda/10 x lambda/10 (2 x 2 voxels at h = lambda/20)
+    and the given length along x."""
+    side = max(1, int(round(0.1 / h)))
+    n = max(1, int(round(length_wavelengths / h)))
+    return box((n, side, side), h, eps=PAPER_EPS, name=f"rod{length_wavelengths:g}L")
+
+
+def paper_slab(side_wavelengths: float, h: float = 1.0 / 20.0) -> Geometry:
+    """Sec. V.C: a slab lambda/10 thick (2 voxels at h = lambda/20), square in x and y."""
+    t = max(1, int(round(0.1 / h)))
+    n = max(1, int(round(side_wavelengths / h)))
+    return box((n, n, t), h, eps=PAPER_EPS, name=f"slab{side_wavelengths:g}L")
+
+
+def paper_cube_array(count: int, cube_voxels: int = 6, h: float = 1.0 / 20.0) -> Geometry:
+    """Sec. V.D: count^3 dielectric cubes of edge 0.3 lambda (cube_voxels at h = lambda/20),
+    neighbours 0.3 lambda apart.  The body is the array's bounding box with eps_r = 1
+    (chi = 0) in the gaps: the gap voxels carry no source and their unknowns are the
+    field there, so the cubes' unknowns solve the same equations as with the cubes
+    alone."""
+    m = count * cube_voxels + (count - 1) * cube_voxels
+    on = (np.arange(m) // cube_voxels) % 2 == 0          # cube, gap, cube, ... along each axis
+    mask = on[:, None, None] & on[None, :, None] & on[None, None, :]
+    e = np.where(mask.reshape(-1), PAPER_EPS, 1.0)
+    return Geometry((m, m, m), h, e.astype(np.complex128), name=f"cubearray{count}",
+                    meta={"count": count, "cube_voxels": cube_voxels})
+

@@ -5,6 +5,8 @@
   phi ~ U[0, 2 pi)), polarisation p = cos(psi) e_theta + sin(psi) e_phi with
   psi ~ U[0, 2 pi), sampled at voxel centres: b[3i+c] = p_c exp(-j k d.r_i)
   (exp(+j omega t) convention, as in g of eq. (1)).
+* paper_excitation: the fixed incidence of Sec. V.B-D, travelling along -y and
+  polarised along z: b[3i+c] = delta_{c,z} exp(+j k y_i).
 """
 
 from __future__ import annotations
@@ -41,3 +43,17 @@ def plane_wave(geom: Geometry, seed: int, count: int = 1) -> np.ndarray:
     phase = np.exp(-1j * geom.k * (r @ d.T))          # (n_vox, count)
     b = phase.T[:, :, None] * p[:, None, :]           # (count, n_vox, 3)
     return b.reshape(count, -1).astype(np.complex128)
+
+
+def plane_wave_dir(geom: Geometry, d, p) -> np.ndarray:
+    """(3*n_vox,) plane wave travelling along the unit vector d with polarisation p."""
+    d = np.asarray(d, np.float64)
+    p = np.asarray(p, np.complex128)
+    phase = np.exp(-1j * geom.k * (geom.centres() @ d))
+    return (phase[:, None] * p[None, :]).reshape(-1).astype(np.complex128)
+
+
+def paper_excitation(geom: Geometry) -> np.ndarray:
+    """Sec. V.B-D: incidence along -y, polarised along z."""
+    return plane_wave_dir(geom, (0.0, -1.0, 0.0), (0.0, 0.0, 1.0))
+
