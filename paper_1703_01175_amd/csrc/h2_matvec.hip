@@ -741,22 +741,16 @@ __global__ __launch_bounds__(256) void k_near_epilogue(
 }
 
 // ---------------------------------------------------------------- tiled near field on the matrix cores
-// Full-mode near field over stored-once blocks, FP64: a group takes a tile of up to
-// kTileLeaves target leaves and walks the tile's steps; a step is one stored block G
+// Full-mode near field over stored-once blocks: a tile is kTileLeaves target leaves
+// consecutive in tree order, walked as a list of steps; a step is one stored block G
 // (n_t x n_s, column-major) and, for each target slot j, the source leaf whose U_s it
 // multiplies (or none).  G is read once per step for all the tile's targets instead of
-// once per leaf pair.  Products are v_mfma_f64_16x16x4f64: A = 16 rows x 4 columns of
-// G, B = 4 rows of U_s x 16 target slots, one 16 x 16 tile per field component; the
-// complex product takes four real ones (re += Gr Ur - Gi Ui, im += Gr Ui + Gi Ur) or,
-// in the 3M form, three (see tile_mma).  This kernel takes any block shape (leaves of
-// fewer than 64 voxels); tiles whose steps are all full 64 x 64 blocks use
-// k_near_tile_split below.
-// Operand layouts: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; result
-// register r of lane l is row 4 r + l / 16, column l % 16.  Waves w and w + 4 own rows
-// 16 (w & 3) .. + 15 and take alternate steps; their sums meet in LDS, then every
-// target's rows are finished as in k_near_epilogue.
-// part 0: the steps, rows left in ypart; 1: ypart finished (leaf backward + epilogue);
-// 2: both in one launch.
+// once per leaf pair.  Products on the matrix cores (A = 16 rows x 4 columns of G, B = 4
+// rows of U_s x 16 target slots, one 16 x 16 tile per field component); the complex
+// product takes four real ones (re += Gr Ur - Gi Ui, im += Gr Ui + Gi Ur) or, in the 3M
+// form, three (see tile_mma).  k_near_tile_split runs the steps (a form for full 64 x 64
+// blocks and one for any shape); k_near_tile_finish finishes every target's rows as
+// k_near_epilogue does.
 // complex products as three real ones (the 3M form: Gr Ur, Gi Ui, (Gr + Gi)(Ur + Ui))
 // instead of four
 constexpr bool kTile3M = true;
@@ -794,23 +788,6 @@ template <typename TV> __device__ __forceinline__ TV cmake(typename Real<TV>::T 
 template <typename TV> struct TileOps {
     TV a, u0, u1, u2;
 };
-
-template <typename TV>
-__device__ __forceinline__ TileOps<TV> tile_load(const TV* __restrict__ gp, const TV* __restrict__ up,
-                                                const TV* __restrict__ zero, int nt, int ns, int k0, int kq) {
-    // columns past n_s take their G entry from the zero block (the address is chosen
-    // before the load, so nothing waits for the loaded value until its use) and read
-    // row 0 of the source
-    const int k = k0 + kq;
-    const bool ok = k < ns;
-    TileOps<TV> o;
-    o.a = *(ok ? gp + (int64_t)k * nt : zero);
-    const TV* u = up + (ok ? k : 0) * kNcomp;
-    o.u0 = u[0];
-    o.u1 = u[1];
-    o.u2 = u[2];
-    return o;
-}
 
 // acc[c][q], component c: with four real products q = 0 re, 1 im; with three (M3,
 // the 3M form) q = 0 Gr Ur, 1 Gi Ui, 2 (Gr + Gi)(Ur + Ui), so re = [0] - [1] and
@@ -869,102 +846,22 @@ __device__ __forceinline__ void tile_total(typename Tile<TV>::V4 (&acc)[3][3], t
     }
 }
 
-template <typename TV, bool M3>
-__global__ __launch_bounds__(512) void k_near_tile(
-    int part, const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf,
-    const int64_t* __restrict__ step_off, const int* __restrict__ step_shape, const int* __restrict__ step_src,
-    const TV* __restrict__ near, const TV* __restrict__ zsrc, TV* __restrict__ ypart,
-    const int* __restrict__ cl_rank, const int* __restrict__ cl_coef, const int* __restrict__ cl_begin,
-    const int* __restrict__ cl_size, const int64_t* __restrict__ cl_basis_off, const TV* __restrict__ basis,
-    const TV* __restrict__ U, const TV* __restrict__ Yh, const int* __restrict__ perm,
-    const TV* __restrict__ x, TV* __restrict__ y, int op, typename Real<TV>::T alpha) {
-    __shared__ TV red[kMaxLeaf][kTileLeaves][kNcomp];
-    const int tile = blockIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int rl = lane & 15, kq = lane >> 4;
-    const int row = 16 * (w & 3) + rl;
-    typename Tile<TV>::V4 acc[3][3], tot[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) acc[c][q] = tot[c][q] = typename Tile<TV>::V4{0, 0, 0, 0};
-    if (part != 1) {
-        const int e = tile_ptr[tile + 1];
-        for (int st = tile_ptr[tile] + (w >> 2); st < e; st += 2) {
-            const int shape = step_shape[st];
-            const int nt = shape & 0xffff, ns = shape >> 16;
-            const int sb = step_src[(int64_t)st * kTileLeaves + rl];
-            // rows past n_t only reach rows that are never finished, so they read row 0;
-            // a slot without a source reads a block of zeros
-            const TV* gp = near + step_off[st] + (row < nt ? row : 0);
-            const TV* up = sb >= 0 ? U + (int64_t)sb * kNcomp : zsrc;
-            // two k steps in flight: each register set is reloaded right after its use,
-            // so no loaded register is copied (a copy would wait for its load)
-            TileOps<TV> p = tile_load(gp, up, zsrc, nt, ns, 0, kq);
-            TileOps<TV> q = tile_load(gp, up, zsrc, nt, ns, 4, kq);
-            // (the scheduling barriers keep each reload where it is written: left alone,
-            // the scheduler sinks every load to just before its use)
-            for (int k0 = 0; k0 < ns; k0 += 8) {
-                tile_mma<M3, TV>(p, acc);
-                p = tile_load(gp, up, zsrc, nt, ns, k0 + 8, kq);
-                __builtin_amdgcn_sched_barrier(0);
-                tile_mma<M3, TV>(q, acc);
-                q = tile_load(gp, up, zsrc, nt, ns, k0 + 12, kq);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            tile_flush<M3, TV>(acc, tot);
-        }
-        tile_total<M3, TV>(acc, tot);
-    }
-    // the two halves' sums meet in LDS: red[row][slot][component]
-    TV v[3][4];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            v[c][r] = M3 ? cmake<TV>(acc[c][0][r] - acc[c][1][r], acc[c][2][r] - acc[c][0][r] - acc[c][1][r])
-                         : cmake<TV>(acc[c][0][r], acc[c][1][r]);
-    const int r0 = 16 * (w & 3);
-    if (w >= 4) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) red[r0 + Tile<TV>::drow(r, kq)][rl][c] = v[c][r];
-    }
-    __syncthreads();
-    if (w < 4) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = r0 + Tile<TV>::drow(r, kq);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) red[i][rl][c] = cadd(red[i][rl][c], v[c][r]);
-        }
-    }
-    __syncthreads();
-    const int pass = part == 1 ? 1 : 0, npass = part == 2 ? 1 : 2;
-    for (int j = w; j < kTileLeaves; j += 8) {
-        const int t = tile_leaf[tile * kTileLeaves + j];
-        if (t < 0) continue;
-        const int n = cl_size[t];
-        if (lane < n)
-            near_finish_row<TV, TV>(t, n, lane, red[lane][j][0], red[lane][j][1], red[lane][j][2], pass,
-                                              npass, ypart, cl_rank, cl_coef, cl_begin, cl_basis_off, basis, Yh,
-                                              perm, x, y, op, alpha);
-    }
-}
-
-// Split form for full blocks: two groups of four waves per tile, taking alternate
+// Two groups of four waves per tile, taking alternate
 // steps, so that a CU holds two groups whose step boundaries (two barriers each: the
 // buffer's reads done, then its refill) fall at different times and one keeps the
 // matrix cores busy while the other refills.  Wave w owns rows 16 w .. + 15 and all 64
 // columns of the block; the group's sources are staged in one LDS buffer; the A
 // operand runs two k steps ahead across steps.  Group h leaves its sums in part[h]
 // (tree order); k_near_tile_finish adds the two and finishes the rows.
-template <typename TV, bool M3>
+// FULL = false takes blocks of any shape n_t x n_s (leaves under 64 voxels): source rows
+// past n_s are staged as zeros, A reads clamp the column to n_s - 1 (a finite value
+// times a zero row) and the row to 0 past n_t (rows that are never stored), and a wave
+// skips the products of k steps past n_s and of rows it holds past n_t.
+template <typename TV, bool M3, bool FULL>
 __global__ __launch_bounds__(256, 2) void k_near_tile_split(
     const int* __restrict__ tile_ptr, const int* __restrict__ tile_leaf, const int64_t* __restrict__ step_off,
-    const int* __restrict__ step_src, const TV* __restrict__ near, const TV* __restrict__ zsrc,
+    const int* __restrict__ step_shape, const int* __restrict__ step_src, const TV* __restrict__ near,
+    const TV* __restrict__ zsrc,
     const int* __restrict__ cl_begin, const int* __restrict__ cl_size, const TV* __restrict__ U,
     TV* __restrict__ part0, TV* __restrict__ part1) {
     constexpr int kSlice = kMaxLeaf * kNcomp;
@@ -986,15 +883,19 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
     const int b = tile_ptr[tile] + h, e = tile_ptr[tile + 1];
     if (b < e) {
         int sb[kChunks];
+        int ns_f = kMaxLeaf;                                    // columns of the block whose sources sb holds
         TV sv[kChunks];
         auto srcs = [&](int st) {
 #pragma unroll
             for (int j = 0; j < kChunks; ++j) sb[j] = step_src[(int64_t)st * kTileLeaves + (tid + 256 * j) / kSlice];
+            if constexpr (!FULL) ns_f = step_shape[st] >> 16;
         };
         auto fetch = [&]() {
 #pragma unroll
-            for (int j = 0; j < kChunks; ++j)
-                sv[j] = *(sb[j] >= 0 ? U + (int64_t)sb[j] * kNcomp + (tid + 256 * j) % kSlice : zsrc);
+            for (int j = 0; j < kChunks; ++j) {
+                const int o = (tid + 256 * j) % kSlice;
+                sv[j] = *(sb[j] >= 0 && (FULL || o / kNcomp < ns_f) ? U + (int64_t)sb[j] * kNcomp + o : zsrc);
+            }
         };
         auto store = [&]() {
 #pragma unroll
@@ -1009,17 +910,42 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
         const int mine = b + ((e - 1 - b) >> 1) * 2;              // this group's last step
         auto last = [&](int st) { return st < e ? st : mine; };   // past the end: re-read the last
         auto aptr = [&](int st) { return near + step_off[st] + row + (int64_t)kq * kMaxLeaf; };
+        // general shapes: the step's block at row min(row, 0 past n_t), its rows n_t apart,
+        // column 4 m + kq of k step m clamped to n_s - 1
+        struct Blk {
+            const TV* p;
+            int nt, ns;
+        };
+        auto blk = [&](int st) {
+            const int sh = step_shape[st];
+            Blk o;
+            o.nt = sh & 0xffff;
+            o.ns = sh >> 16;
+            o.p = near + step_off[st] + (row < o.nt ? row : 0);
+            return o;
+        };
+        auto aload = [&](const Blk& o, int m) { return o.p[(int64_t)min(4 * m + kq, o.ns - 1) * o.nt]; };
         srcs(b);
         fetch();
         store();
         srcs(last(b + 2));
         const TV* ga = aptr(b);
-        TV a0 = ga[0], a1 = ga[4 * kMaxLeaf];
+        Blk ca, na;
+        TV a0, a1;
+        if constexpr (FULL) {
+            a0 = ga[0];
+            a1 = ga[4 * kMaxLeaf];
+        } else {
+            ca = blk(b);
+            a0 = aload(ca, 0);
+            a1 = aload(ca, 1);
+        }
         __syncthreads();
         for (int st = b; st < e; st += 2) {
             fetch();                                            // slices of step st + 2
             srcs(last(st + 4));
             const TV* gn = aptr(last(st + 2));
+            if constexpr (!FULL) na = blk(last(st + 2));
             const TV* bs = &stage[0][0][0] + (kq * kTileLeaves + rl) * kNcomp;
             TV bu[2][3];
 #pragma unroll
@@ -1035,16 +961,22 @@ __global__ __launch_bounds__(256, 2) void k_near_tile_split(
                 o.u0 = bu[i & 1][0];
                 o.u1 = bu[i & 1][1];
                 o.u2 = bu[i & 1][2];
-                tile_mma<M3, TV>(o, acc);
-                const TV* src = i + 2 < kSteps ? ga + (i + 2) * 4 * kMaxLeaf : gn + (i + 2 - kSteps) * 4 * kMaxLeaf;
+                if (FULL || (4 * i < ca.ns && 16 * w < ca.nt)) tile_mma<M3, TV>(o, acc);
+                TV an;
+                if constexpr (FULL) {
+                    an = *(i + 2 < kSteps ? ga + (i + 2) * 4 * kMaxLeaf : gn + (i + 2 - kSteps) * 4 * kMaxLeaf);
+                } else {
+                    an = i + 2 < kSteps ? aload(ca, i + 2) : aload(na, i + 2 - kSteps);
+                }
                 if (i & 1)
-                    a1 = *src;
+                    a1 = an;
                 else
-                    a0 = *src;
+                    a0 = an;
                 __builtin_amdgcn_sched_barrier(0);
             }
             tile_flush<M3, TV>(acc, tot);
             ga = gn;
+            if constexpr (!FULL) ca = na;
             __syncthreads();                                    // every wave is done with the buffer
             store();
             __syncthreads();
@@ -1309,21 +1241,16 @@ static hipError_t matvec_tier(const DevH2& d, const LevelLaunch& lv, int op, con
     const bool overlap = !d.near_sym && d.near_side && (tiles || d.near_passes > 1);
     auto near_tile = [&](int part, const TV* xr, TV* yr, hipStream_t st) {
         if constexpr (same) {
-            if (d.tiles_full) {
-                if (part != 1)
-                    k_near_tile_split<TV, kTile3M><<<2 * d.n_tiles, 256, 0, st>>>(
-                        d.tile_ptr, d.tile_leaf, d.step_off, d.step_src, near, (const TV*)d.zero_block, d.cl_begin,
-                        d.cl_size, U, (TV*)d.near_ypart, (TV*)d.tile_part1);
-                if (part != 0)
-                    k_near_tile_finish<TV><<<d.n_leaves, 64, 0, st>>>(
-                        d.leaf_id, (const TV*)d.near_ypart, (const TV*)d.tile_part1, d.cl_rank, d.cl_coef,
-                        d.cl_begin, d.cl_size, d.cl_basis_off, basis, Yh, d.perm, xr, yr, op, alpha);
-            } else {
-                k_near_tile<TV, kTile3M><<<d.n_tiles, 512, 0, st>>>(
-                    part, d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src, near, (const TV*)d.zero_block,
-                    (TV*)d.near_ypart, d.cl_rank, d.cl_coef, d.cl_begin, d.cl_size, d.cl_basis_off, basis, U, Yh,
-                    d.perm, xr, yr, op, alpha);
+            if (part != 1) {
+                auto split = d.tiles_full ? k_near_tile_split<TV, kTile3M, true> : k_near_tile_split<TV, kTile3M, false>;
+                split<<<2 * d.n_tiles, 256, 0, st>>>(d.tile_ptr, d.tile_leaf, d.step_off, d.step_shape, d.step_src,
+                                                     near, (const TV*)d.zero_block, d.cl_begin, d.cl_size, U,
+                                                     (TV*)d.near_ypart, (TV*)d.tile_part1);
             }
+            if (part != 0)
+                k_near_tile_finish<TV><<<d.n_leaves, 64, 0, st>>>(
+                    d.leaf_id, (const TV*)d.near_ypart, (const TV*)d.tile_part1, d.cl_rank, d.cl_coef, d.cl_begin,
+                    d.cl_size, d.cl_basis_off, basis, Yh, d.perm, xr, yr, op, alpha);
         }
     };
     auto near_kernel = d.near_cached ? k_near_epilogue<TB, TV, false> : k_near_epilogue<TB, TV, true>;
