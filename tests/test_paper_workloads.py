@@ -68,3 +68,22 @@ def test_rod_rank_and_iterations_do_not_grow_with_length():
         its.append(rep.iterations)
     assert max(ranks) == min(ranks)
     assert max(its) <= its[0]
+
+
+def test_cube_array_gaps_do_not_change_the_cubes_equations():
+    """The array of cubes is solved on its bounding box with chi = 0 in the gaps: the gap
+    columns of Z are identity columns, and the cube voxels' part of the box solution
+    solves the system restricted to the cube voxels alone."""
+    from oracle.kernel import dense_G
+    g = h2gen.paper_cube_array(2, cube_voxels=2)            # 6^3 box, 8 cubes of 2^3 voxels
+    n = g.n_vox
+    G = dense_G(g.shape, g.h, g.k)
+    Zs = np.eye(n) + g.sigma * g.k ** 2 * g.volume * G * g.chi[None, :]   # scalar Z, one component
+    gap = g.chi == 0
+    assert gap.sum() == 6 ** 3 - 8 * 2 ** 3
+    assert np.array_equal(Zs[:, gap], np.eye(n)[:, gap])
+    b = h2gen.paper_excitation(g).reshape(n, 3)[:, 2]
+    x = np.linalg.solve(Zs, b)
+    cubes = ~gap
+    xc = np.linalg.solve(Zs[np.ix_(cubes, cubes)], b[cubes])
+    assert np.linalg.norm(x[cubes] - xc) <= 1e-12 * np.linalg.norm(xc)
