@@ -219,6 +219,10 @@ def main():
         log(f"[bench] couplings symmetrised (S_st := S_ts^T) in {time.time() - t0:.1f}s")
     x_np = h2gen.random_vector(3 * g.n_vox, 1)
     b_np = h2gen.plane_wave(g, seed)[0]
+    # the precision tiers on the 12^3 cube's representation (also built before the GPU)
+    e12, s12, r12, seed12, eps12 = WORKLOADS["cube12"]
+    g12 = h2gen.cube(e12, s12, r12, seed=seed12, name="cube12")
+    d12 = build_h2(g12, eps=eps12)
 
     import torch
     from paper_1703_01175_amd import H2Operator
@@ -253,6 +257,10 @@ def main():
             np.linalg.norm(y.cpu().numpy() - result_gpu) / np.linalg.norm(result_gpu))
         H.near_tiles(True)
     extra["fp32_tier_product"] = fp32_product_leg(H, x, result_gpu, args.steps, args.warmup)
+    try:
+        extra["tiers_cube12"] = tier_leg(g12, d12, dev)
+    except Exception as e:                 # an auxiliary leg: its failure is reported, not fatal
+        extra["tiers_cube12"] = {"error": repr(e)}
     if not args.no_solve:
         extra.update(solve_legs(H, b_np, dev))
     if not args.keep_all_near and not args.no_streamed:
@@ -327,6 +335,38 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def tier_leg(g, d, dev):
+    """The 12^3 cube (0.5 wavelength, eps_r 4, eps 1e-4) in every precision tier: each tier's
+    product error against the FP64 product (x ~ CN(0, 1), seed 1), and GMRES(50) to a 1e-6
+    FP64 residual on a plane wave (seed 1) with each tier's products inside iterative
+    refinement (FP64: plain GMRES)."""
+    import numpy as np
+    import torch
+    import h2gen
+    from paper_1703_01175_amd import H2Operator
+    H = H2Operator(d, tiers=("fp64", "fp32", "bf16x3"), max_rhs=1, device="cuda:0")
+    x = h2gen.random_vector(3 * g.n_vox, 1)
+    y64 = H.matvec(torch.from_numpy(x).to(dev)).cpu().numpy()
+    x32 = torch.from_numpy(x.astype(np.complex64)).to(dev)
+    out = {"workload": "cube12: 12^3 voxels, 0.5 wavelengths per side, eps_r 4, eps 1e-4", "N": 3 * g.n_vox}
+    for tier in ("fp32", "bf16x3"):
+        y = H.matvec(x32, precision=tier).cpu().numpy().astype(np.complex128)
+        out[f"{tier}_product_rel_err_vs_fp64"] = float(np.linalg.norm(y - y64) / np.linalg.norm(y64))
+    b = torch.from_numpy(h2gen.plane_wave(g, 1)[0]).to(dev)
+    for tier in ("fp64", "fp32", "bf16x3"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, rep = H.gmres(b, tol=1e-6, restart=50, precision=tier, inner_tol=1e-3)
+        torch.cuda.synchronize()
+        out[f"gmres_{tier}"] = {"seconds": round(time.time() - t0, 4), "iterations": rep.iterations,
+                                "outer": rep.outer, "matvecs": rep.matvecs, "converged": rep.converged,
+                                "rel_residual": rep.rel_residual}
+    H.close()
+    log(f"[bench] tiers on cube12: product errors fp32 {out['fp32_product_rel_err_vs_fp64']:.2e}, "
+        f"bf16x3 {out['bf16x3_product_rel_err_vs_fp64']:.2e}")
+    return out
 
 
 def fp32_product_leg(H, x, y64, steps, warmup):
